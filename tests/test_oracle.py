@@ -1,0 +1,308 @@
+"""Pins for the CPU oracle (no GPU).
+
+The oracle (recursive stable binar partition) is checked against things it
+does not share code with: the paper's printed worked example, brute force over
+all orderings, Python's and numpy's stable sorts (library special cases),
+invariants written separately below, closed forms, and the bit-step bound of
+the time analysis.
+"""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import definition
+from oracle.swap_partition import binar_swap_sort
+import workloads
+
+HEX = "0123456789ABCDEF"
+
+
+def nyb(xs):
+    return [HEX.index(x) for x in xs]
+
+
+# ---------------------------------------------------------------- invariants
+def check_invariants(keys_in, keys_out, pay_out):
+    """Permutation + gather + nondecreasing + stable; together these fix the
+    stable sort uniquely.  Comparison is on big-endian bytes (the encoding)."""
+    n = keys_in.shape[0]
+    assert keys_out.shape == keys_in.shape
+    seen = np.zeros(n, dtype=bool)
+    seen[pay_out.astype(np.int64)] = True
+    assert seen.all(), "payload is not a permutation"
+    assert np.array_equal(keys_in[pay_out.astype(np.int64)], keys_out), "keys_out != keys_in[p]"
+    for i in range(n - 1):
+        a = definition.bit_string(keys_out, i)
+        b = definition.bit_string(keys_out, i + 1)
+        assert a <= b, "not nondecreasing at %d" % i
+        if a == b:
+            assert pay_out[i] < pay_out[i + 1], "unstable tie at %d" % i
+
+
+def iota(n):
+    return np.arange(n, dtype=np.uint32)
+
+
+# ------------------------------------------------------ paper's worked example
+@pytest.fixture(scope="module")
+def example(golden_dir):
+    with open(os.path.join(golden_dir, "worked_example.json")) as f:
+        return json.load(f)
+
+
+def test_swap_partition_reproduces_printed_configurations(example):
+    trace = []
+    out = binar_swap_sort(nyb(example["input"]), example["key_bits"], trace)
+    assert out == nyb(example["sorted"])
+    calls = {(b, lo, hi): states for (b, lo, hi, states) in trace}
+    for name, bit in (("first_pass_bit1", 0), ("lower_subarray_bit2", 1), ("upper_subarray_bit2", 1)):
+        t = example["traces"][name]
+        lo, hi = t["bounds"]
+        got = calls[(bit, lo, hi)]
+        want = [tuple(nyb(part) for part in st) for st in t["states"]]
+        assert [tuple(list(p) for p in st) for st in got] == [tuple(list(p) for p in st) for st in want]
+
+
+def test_oracle_sorts_worked_example(example):
+    keys = np.array(nyb(example["input"]), dtype=np.uint64)
+    k, p, steps = oracle.sort_bits(keys, 4, iota(8), with_steps=True)
+    assert k.tolist() == nyb(example["sorted"])
+    # the two 0s keep input order (indices 2 then 3): the stable permutation
+    assert p.tolist() == [2, 3, 1, 4, 5, 0, 6, 7]
+    assert steps <= 4 * 8
+
+
+def groups_after(keys_u64, nbits, width):
+    """Split a partially partitioned array into runs of equal top-nbits prefix."""
+    out, cur, prev = [], [], None
+    for v in keys_u64.tolist():
+        pre = v >> (width - nbits)
+        if prev is not None and pre != prev:
+            out.append(cur)
+            cur = []
+        cur.append(v)
+        prev = pre
+    if cur:
+        out.append(cur)
+    return out
+
+
+def test_oracle_partial_states_match_printed_summary(example):
+    keys = np.array(nyb(example["input"]), dtype=np.uint64)
+    for b in (1, 2, 3, 4):
+        k, _ = oracle.sort_bits(keys, 4, iota(8), nbits=b)
+        got = [sorted(g) for g in groups_after(k, b, 4)]
+        want = [sorted(nyb(g)) for g in example["reading_of_summary"]["bit%d" % b]]
+        assert got == want, b
+        if b <= 2:  # the printed rows for bits 1 and 2 agree with the bits
+            printed = [sorted(nyb(g)) for g in example["printed_summary"]["bit%d" % b]]
+            assert got == printed
+    # stable order inside the groups after bit 1: input order of each group
+    k, p = oracle.sort_bits(keys, 4, iota(8), nbits=1)
+    assert [HEX[v] for v in k.tolist()] == list("4007BACE")
+    assert p.tolist() == [1, 2, 3, 4, 0, 5, 6, 7]
+
+
+def test_pins_detect_unstable_partition(example):
+    """The paper's exchange partition swaps the two equal 0s; the stability
+    invariant must reject it (a planted mistake, on the CPU)."""
+    vals = nyb(example["input"])
+    a = list(vals)
+    idx = list(range(8))
+    binar_swap_sort(a, 4, payload=idx)
+    keys_in = np.array(vals, dtype=np.uint32)
+    with pytest.raises(AssertionError):
+        check_invariants(keys_in, np.array(a, dtype=np.uint32), np.array(idx, dtype=np.uint32))
+    assert idx == [3, 2, 1, 4, 5, 0, 6, 7]
+
+
+# ------------------------------------------------------------- brute force
+def brute_force_stable(keys):
+    """Enumerate every ordering; keep those that are nondecreasing and keep
+    equal keys in input order.  Exactly one must survive."""
+    n = keys.shape[0]
+    enc = [definition.bit_string(keys, i) for i in range(n)]
+    found = []
+    for perm in itertools.permutations(range(n)):
+        ok = True
+        for a, b in zip(perm, perm[1:]):
+            if enc[a] > enc[b] or (enc[a] == enc[b] and a > b):
+                ok = False
+                break
+        if ok:
+            found.append(perm)
+    assert len(found) == 1
+    return list(found[0])
+
+
+U32_EDGE = [0, 1, 0x7FFFFFFF, 0x80000000, 0xFFFFFFFF, 0x80000001, 0x00010000]
+
+
+@pytest.mark.parametrize("n,seed", [(0, 1), (1, 2), (2, 3), (3, 4), (5, 5), (6, 6), (7, 7), (8, 8)])
+def test_brute_force_u32(n, seed):
+    keys = workloads.small_alphabet_u32(n, seed, U32_EDGE[: 3 + seed % 5])
+    want = brute_force_stable(keys) if n else []
+    k, p = oracle.sort(keys, iota(n))
+    assert p.tolist() == want
+    assert k.tolist() == keys[np.array(want, dtype=np.int64)].tolist()
+
+
+@pytest.mark.parametrize("n,seed", [(4, 11), (6, 12), (7, 13)])
+def test_brute_force_u64(n, seed):
+    alphabet = np.array([0, 1 << 63, (1 << 63) - 1, 0xFFFFFFFF, 1 << 32, (1 << 64) - 1], dtype=np.uint64)
+    keys = alphabet[workloads.below(n, seed, len(alphabet)).astype(np.int64)]
+    want = brute_force_stable(keys)
+    k, p = oracle.sort(keys, iota(n))
+    assert p.tolist() == want
+
+
+@pytest.mark.parametrize("n,seed", [(5, 21), (7, 22)])
+def test_brute_force_str16(n, seed):
+    base = np.frombuffer(b"abcdefghijklmnop", dtype=np.uint8)
+    alphabet = np.stack([base.copy() for _ in range(5)])
+    alphabet[1, 0] = ord("b") - 1   # differs in the first byte
+    alphabet[2, 15] = ord("a")      # differs in the last byte
+    alphabet[3, 0] = 0xFF           # high bit of the first byte
+    alphabet[4, 15] = 0x80
+    keys = alphabet[workloads.below(n, seed, 5).astype(np.int64)]
+    want = brute_force_stable(keys)
+    k, p = oracle.sort(keys, iota(n))
+    assert p.tolist() == want
+
+
+# ------------------------------------------------- library special cases
+@pytest.mark.parametrize("n,seed", [(1000, 31), (4097, 32), (100_000, 33)])
+def test_matches_numpy_stable_argsort_u32(n, seed):
+    keys = workloads.u32_uniform(n, seed)
+    m = keys[::11].shape[0]
+    keys[: 7 * m : 7] = keys[::11]  # inject ties
+    k, p = oracle.sort(keys, iota(n))
+    ref = np.argsort(keys, kind="stable")
+    assert np.array_equal(p, ref.astype(np.uint32))
+    assert np.array_equal(k, keys[ref])
+
+
+@pytest.mark.parametrize("gen", ["uniform", "dup", "zipf", "nearly"])
+def test_matches_numpy_stable_argsort_u64(gen):
+    n = 20_000
+    keys = {"uniform": lambda: workloads.u64_uniform(n, 41),
+            "dup": lambda: workloads.u64_uniform(64, 42)[workloads.below(n, 43, 64).astype(np.int64)],
+            "zipf": lambda: workloads.u64_zipf(n, 44, 1 << 10, 1.1),
+            "nearly": lambda: workloads.u64_nearly_sorted(n, 45, 0.01)}[gen]()
+    k, p = oracle.sort(keys, iota(n))
+    ref = np.argsort(keys, kind="stable")
+    assert np.array_equal(p, ref.astype(np.uint32))
+
+
+def test_matches_stable_lexsort_str16():
+    n = 5000
+    keys = workloads.str16(n, 51, 6)
+    m = keys[1::3].shape[0]
+    keys[: 3 * m : 3] = keys[1::3]
+    k, p = oracle.sort(keys, iota(n))
+    ref = np.lexsort(tuple(keys[:, c] for c in range(15, -1, -1)))  # byte 0 is the primary key
+    assert np.array_equal(p, ref.astype(np.uint32))
+
+
+@pytest.mark.parametrize("kind,seed", [("u32", 61), ("u64", 62), ("str", 63), ("u32ties", 64)])
+def test_matches_plain_definition(kind, seed):
+    n = 1500
+    keys = {"u32": lambda: workloads.u32_uniform(n, seed),
+            "u64": lambda: workloads.u64_uniform(n, seed),
+            "str": lambda: workloads.str16(n, seed, 10),
+            "u32ties": lambda: workloads.small_alphabet_u32(n, seed, U32_EDGE)}[kind]()
+    k, p = oracle.sort(keys, iota(n))
+    dk, dp = definition.sort(keys, iota(n))
+    assert np.array_equal(p, dp)
+    assert np.array_equal(k, dk)
+    check_invariants(keys, k, p)
+
+
+# ---------------------------------------------------------- closed forms
+def test_closed_forms():
+    n = 777
+    same = np.full(n, 0xDEADBEEF, dtype=np.uint32)
+    _, p = oracle.sort(same, iota(n))
+    assert np.array_equal(p, iota(n))                         # all equal -> identity
+    inc = np.arange(n, dtype=np.uint32) * 3 + 5
+    _, p = oracle.sort(inc, iota(n))
+    assert np.array_equal(p, iota(n))                         # increasing -> identity
+    dec = inc[::-1].copy()
+    k, p = oracle.sort(dec, iota(n))
+    assert np.array_equal(p, iota(n)[::-1])                   # decreasing distinct -> reversal
+    assert np.array_equal(k, inc)
+
+
+@pytest.mark.parametrize("bit", [0, 1, 15, 31])
+def test_one_bit_difference_splits_at_that_bit(bit):
+    n = 300
+    base = np.uint32(0x5A5A5A5A) & ~np.uint32(1 << (31 - bit))
+    sel = workloads.below(n, 70 + bit, 2).astype(bool)
+    keys = np.where(sel, base | np.uint32(1 << (31 - bit)), base).astype(np.uint32)
+    # before partitioning bit `bit` nothing moves; after it the zeros lead
+    k0, p0 = oracle.partition(keys, iota(n), bit)
+    assert np.array_equal(p0, iota(n))
+    k1, p1 = oracle.partition(keys, iota(n), bit + 1)
+    zeros = np.flatnonzero(~sel).astype(np.uint32)
+    ones = np.flatnonzero(sel).astype(np.uint32)
+    assert np.array_equal(p1, np.concatenate([zeros, ones]))
+
+
+def test_partial_partition_equals_stable_sort_by_prefix():
+    n = 50_000
+    keys = workloads.u32_uniform(n, 81)
+    for nbits in (1, 4, 8, 13, 16, 24, 32):
+        k, p = oracle.partition(keys, iota(n), nbits)
+        prefix = keys >> np.uint32(32 - nbits) if nbits < 32 else keys
+        ref = np.argsort(prefix, kind="stable")
+        assert np.array_equal(p, ref.astype(np.uint32)), nbits
+
+
+def test_bit_step_bound():
+    """Section "Recursion Analysis": at most (bits per key) visits per element."""
+    for kb, keys in ((4, workloads.u32_uniform(30_000, 91)), (8, workloads.u64_uniform(30_000, 92)),
+                     (16, workloads.str16(30_000, 93, 0))):
+        n = keys.shape[0]
+        _, _, steps = oracle.sort(keys, None, with_steps=True)
+        assert 0 < steps <= 8 * kb * n
+    # distinct keys with all bits examined: uniform u32 needs ~log2(n) levels each
+    _, _, steps = oracle.sort(workloads.u32_uniform(1 << 14, 94), None, with_steps=True)
+    assert steps >= 14 * (1 << 14) * 0.9
+
+
+def test_small_and_empty():
+    for n in (0, 1, 2):
+        keys = workloads.u32_uniform(n, 100 + n)
+        k, p = oracle.sort(keys, iota(n))
+        assert sorted(keys.tolist()) == k.tolist()
+    k, p = oracle.sort(np.array([5, 5], dtype=np.uint32), iota(2))
+    assert p.tolist() == [0, 1]
+    k, p = oracle.sort(np.array([0x80000000, 0x7FFFFFFF], dtype=np.uint32), iota(2))
+    assert p.tolist() == [1, 0]
+
+
+def test_segmented_is_per_segment():
+    keys, off = workloads.batched_u32(200, seed=7, median=64, sigma=1.0, max_len=4000)
+    n = keys.shape[0]
+    off[5] = off[4]  # an empty segment
+    k, p = oracle.sort_segmented(keys, off, iota(n))
+    for s in range(200):
+        a, b = int(off[s]), int(off[s + 1])
+        if b < a:
+            continue
+        ref = np.argsort(keys[a:b], kind="stable").astype(np.uint32) + np.uint32(a)
+        assert np.array_equal(p[a:b], ref), s
+
+
+def test_appendix_exchange_sort_agrees_on_keys():
+    """The paper's unstable exchange partition yields the same key order."""
+    for seed in range(5):
+        vals = workloads.u32_uniform(3000, 200 + seed)
+        vals = (vals >> np.uint32(20)).astype(np.uint64)  # 12-bit keys: many ties
+        out = binar_swap_sort(vals.tolist(), 12)
+        k, _ = oracle.sort_bits(vals, 12)
+        assert out == k.tolist()
