@@ -1,0 +1,140 @@
+/*
+ * binar.h -- C ABI of the MI355X (gfx950) binar sort library, libbinar.so.
+ *
+ * The operation (Gilreath, "Binar Sort", section "Sorting Formalism", with
+ * the stability tie-break): rearrange n keys in place into nondecreasing
+ * order of their bit strings, most significant bit first, and rearrange an
+ * optional uint32 payload with them.  Equal keys keep their input order, so
+ * the result is unique; a payload of 0,1,...,n-1 comes back as the sorting
+ * permutation p (0-based): payload_out[i] = payload_in[p(i)].
+ *
+ * The method (sections "Algorithm Synopsis", "Operation of Algorithm",
+ * "Algorithm Variants"): partition on the most significant bit(s) first and
+ * continue on every sub-array with the next bits, stopping when a sub-array
+ * has one element or the bits are used up.  Here every partition is stable,
+ * k bits are taken per pass (a stable 2^k-way partition is k stable binary
+ * partitions in a row), all live sub-arrays are partitioned in one
+ * breadth-first pass, and sub-arrays small enough for on-chip memory are
+ * finished by one workgroup each.
+ *
+ * Key views (section "The Other Universal Property": the encoding is what
+ * is sorted):
+ *   key_bytes == 4  : uint32 values (native little-endian), numeric order;
+ *   key_bytes == 8  : uint64 values (native little-endian), numeric order;
+ *   key_bytes == 16 : 16-byte strings, memcmp order.
+ * Signed and floating-point keys are not reinterpreted: their bit patterns
+ * sort as unsigned integers.
+ *
+ * Memory and ownership:
+ *   keys, payload, seg_offsets are DEVICE pointers owned by the caller; keys
+ *   and payload are sorted in place.  The library never frees caller memory.
+ *   Scratch memory is either the caller's `workspace` (device, at least
+ *   binar_workspace_bytes() bytes, 256-byte aligned) or, when workspace is
+ *   NULL, a per-device pool the library grows on demand and keeps until the
+ *   process ends.  Two calls that share a workspace (or the pool) must not
+ *   overlap in time.
+ *   `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *
+ * Limits: n (or the sum of segment lengths) < 2^30, because the decoupled
+ * look-back packs a prefix count and a 2-bit flag into one 32-bit word.
+ *
+ * Errors: every call returns a status code.  Arguments are checked before
+ * any device work is enqueued, so on an error the caller's buffers are not
+ * touched.  Segment offsets live on the device and are checked on the
+ * device: an invalid table makes every kernel of that call exit without
+ * writing caller memory and is reported by the synchronous calls (and by
+ * binar_stats_read) as BINAR_EINVAL.  The _async calls report enqueue
+ * errors only; device faults surface at the caller's synchronisation.
+ * No C++ exception crosses this interface.
+ */
+#ifndef BINAR_H
+#define BINAR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BINAR_OK 0
+#define BINAR_EINVAL (-1)  /* bad key_bytes, NULL pointer with n > 0, bad segment table */
+#define BINAR_ERANGE (-2)  /* n or total segment length >= 2^30 */
+#define BINAR_ENOMEM (-3)  /* workspace too small, or the pool could not grow */
+#define BINAR_EDEVICE (-4) /* a HIP call failed */
+
+#define BINAR_MAX_KEYS ((1u << 30) - 1u)
+
+/* Tuning knobs; a zero field means "library default".
+ *   digit_bits : bits taken per global pass, 1..8 (1 = the paper's binary
+ *                partition step, made stable).
+ *   tile_keys  : keys per scatter tile, one of 2048, 4096, 8192.
+ *   finish_max : largest sub-array finished in on-chip memory (LDS) by one
+ *                workgroup; capped by the key width's largest LDS class. */
+typedef struct binar_params {
+    uint32_t digit_bits;
+    uint32_t tile_keys;
+    uint32_t finish_max;
+    uint32_t reserved;
+} binar_params;
+
+/* Counters of the last call that used a workspace (exact integers).
+ *   moved[j]       keys scattered by global pass j (pass-through and
+ *                  finished sub-arrays move nothing);
+ *   hist_keys[j]   keys read by the digit count of pass j;
+ *   finish_keys    keys sorted in LDS; finish_segments their sub-arrays;
+ *   passes         global passes that had work. */
+typedef struct binar_stats {
+    uint64_t moved[16];
+    uint64_t hist_keys[16];
+    uint64_t finish_keys;
+    uint64_t finish_segments;
+    uint32_t passes;
+    int32_t status;
+} binar_stats;
+
+/* Sort n keys (and payload, may be NULL) on the null stream with the pool;
+ * blocks until the sort has finished. */
+int binar_sort(void *keys, uint32_t key_bytes, uint64_t n, uint32_t *payload);
+
+/* Enqueue the same sort on `stream`; returns once enqueued.  workspace may be
+ * NULL (pool). */
+int binar_sort_async(void *keys, uint32_t key_bytes, uint64_t n, uint32_t *payload,
+                     void *stream, void *workspace, size_t workspace_bytes);
+
+/* Sort each segment [seg_offsets[s], seg_offsets[s+1]) of keys independently
+ * (payload permuted within its segment), all in one enqueue sequence.
+ * seg_offsets: device uint32[num_segments + 1], nondecreasing, in keys;
+ * n_total: an upper bound on seg_offsets[num_segments] used to size the
+ * scratch (the device checks the table against it).  Empty segments are
+ * allowed.  Enqueue only. */
+int binar_sort_segmented(void *keys, uint32_t key_bytes, const uint32_t *seg_offsets,
+                         uint32_t num_segments, uint64_t n_total, uint32_t *payload,
+                         void *stream, void *workspace, size_t workspace_bytes);
+
+/* Same calls with explicit tuning knobs (params may be NULL). */
+int binar_sort_ex(void *keys, uint32_t key_bytes, uint64_t n, uint32_t *payload,
+                  const uint32_t *seg_offsets, uint32_t num_segments,
+                  const binar_params *params, void *stream, void *workspace,
+                  size_t workspace_bytes);
+
+/* Scratch bytes a call needs (0 on invalid arguments).  params may be NULL. */
+size_t binar_workspace_bytes(uint32_t key_bytes, uint64_t n, int has_payload,
+                             uint32_t num_segments, const binar_params *params);
+
+/* Read the counters of the last call that used `workspace` (NULL = the
+ * calling device's pool), after synchronising `stream`. */
+int binar_stats_read(const void *workspace, void *stream, binar_stats *out);
+
+/* The defaults binar_sort uses; set by the autotuner.  key_bytes 4, 8, 16. */
+int binar_get_default_params(uint32_t key_bytes, int has_payload, binar_params *out);
+int binar_set_default_params(uint32_t key_bytes, int has_payload, const binar_params *p);
+
+/* Static description of a status code. */
+const char *binar_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BINAR_H */

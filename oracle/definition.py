@@ -35,3 +35,11 @@ def sort(keys: np.ndarray, payload: np.ndarray | None = None):
     out_k = keys[p] if keys.shape[0] else keys.copy()
     out_p = None if payload is None else np.asarray(payload)[p]
     return out_k, out_p
+
+
+def stable_rank_u(keys: np.ndarray, j: int) -> int:
+    """Output position of input element j under the stable sort of unsigned
+    integer keys: keys strictly smaller, plus equal keys earlier in the
+    input.  One output at a time, for spot checks of very large sorts."""
+    kj = keys[j]
+    return int(np.count_nonzero(keys < kj)) + int(np.count_nonzero(keys[:j] == kj))

@@ -1,0 +1,180 @@
+"""ctypes binding of libbinar.so (argument marshalling only).
+
+The library must have been built (``python -m paper_0811_3448_amd.build``);
+importing this module without it raises ImportError -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbinar.so")
+
+BINAR_OK, BINAR_EINVAL, BINAR_ERANGE, BINAR_ENOMEM, BINAR_EDEVICE = 0, -1, -2, -3, -4
+MAX_KEYS = (1 << 30) - 1
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("digit_bits", ctypes.c_uint32), ("tile_keys", ctypes.c_uint32),
+                ("finish_max", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("moved", ctypes.c_uint64 * 16), ("hist_keys", ctypes.c_uint64 * 16),
+                ("finish_keys", ctypes.c_uint64), ("finish_segments", ctypes.c_uint64),
+                ("passes", ctypes.c_uint32), ("status", ctypes.c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libbinar.so is not built (%s); run python -m paper_0811_3448_amd.build" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    vp, u32, u64, sz, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t, ctypes.c_int
+    P = ctypes.POINTER(_Params)
+    L.binar_sort.argtypes = [vp, u32, u64, vp]
+    L.binar_sort_async.argtypes = [vp, u32, u64, vp, vp, vp, sz]
+    L.binar_sort_segmented.argtypes = [vp, u32, vp, u32, u64, vp, vp, vp, sz]
+    L.binar_sort_ex.argtypes = [vp, u32, u64, vp, vp, u32, P, vp, vp, sz]
+    L.binar_workspace_bytes.argtypes = [u32, u64, i32, u32, P]
+    L.binar_workspace_bytes.restype = sz
+    L.binar_stats_read.argtypes = [vp, vp, ctypes.POINTER(_Stats)]
+    L.binar_get_default_params.argtypes = [u32, i32, P]
+    L.binar_set_default_params.argtypes = [u32, i32, P]
+    L.binar_strerror.argtypes = [i32]
+    L.binar_strerror.restype = ctypes.c_char_p
+    for f in ("binar_sort", "binar_sort_async", "binar_sort_segmented", "binar_sort_ex",
+              "binar_stats_read", "binar_get_default_params", "binar_set_default_params"):
+        getattr(L, f).restype = i32
+    return L
+
+
+lib = _load()
+
+
+class BinarError(RuntimeError):
+    def __init__(self, status: int):
+        self.status = status
+        super().__init__("binar: %s (status %d)" % (strerror(status), status))
+
+
+def strerror(status: int) -> str:
+    return lib.binar_strerror(status).decode()
+
+
+def _check(rc: int) -> None:
+    if rc != BINAR_OK:
+        raise BinarError(rc)
+
+
+@dataclass
+class Params:
+    digit_bits: int = 0
+    tile_keys: int = 0
+    finish_max: int = 0
+
+    def c(self):
+        return _Params(self.digit_bits, self.tile_keys, self.finish_max, 0)
+
+
+def key_bytes_of(keys) -> int:
+    """4 / 8 for 1-D tensors of 4- / 8-byte elements, 16 for uint8 (n, 16)."""
+    import torch
+    if keys.dim() == 1 and keys.element_size() in (4, 8):
+        return keys.element_size()
+    if keys.dim() == 2 and keys.dtype == torch.uint8 and keys.shape[1] == 16:
+        return 16
+    raise ValueError("keys must be 1-D with 4- or 8-byte elements, or uint8 of shape (n, 16)")
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _check_tensors(keys, payload):
+    if not keys.is_cuda or not keys.is_contiguous():
+        raise ValueError("keys must be a contiguous device tensor")
+    if payload is not None:
+        if not payload.is_cuda or not payload.is_contiguous() or payload.element_size() != 4 \
+                or payload.dim() != 1 or payload.shape[0] != keys.shape[0]:
+            raise ValueError("payload must be a contiguous 1-D 4-byte device tensor of the keys' length")
+
+
+class Workspace:
+    """Caller-owned scratch: a device uint8 tensor of the required size."""
+
+    def __init__(self, nbytes: int, device=None):
+        import torch
+        self.nbytes = int(nbytes)
+        self.tensor = torch.empty(max(self.nbytes, 256), dtype=torch.uint8, device=device or "cuda")
+
+    @property
+    def ptr(self):
+        return ctypes.c_void_p(self.tensor.data_ptr())
+
+
+def workspace_bytes(key_bytes: int, n: int, has_payload: bool, num_segments: int = 1,
+                    params: Params | None = None) -> int:
+    p = None if params is None else ctypes.byref(params.c())
+    return int(lib.binar_workspace_bytes(key_bytes, n, 1 if has_payload else 0, num_segments, p))
+
+
+def sort(keys, payload=None, stream=None, workspace: Workspace | None = None,
+         params: Params | None = None):
+    """Sort keys (and payload) in place on `stream` (default: torch's current
+    stream).  Returns keys.  Asynchronous like any torch op."""
+    _check_tensors(keys, payload)
+    kb = key_bytes_of(keys)
+    n = keys.shape[0]
+    ws = (None, 0) if workspace is None else (workspace.ptr, workspace.nbytes)
+    pp = None if params is None else ctypes.byref(params.c())
+    _check(lib.binar_sort_ex(_dev_ptr(keys), kb, n, _dev_ptr(payload), None, 0, pp,
+                             _stream_ptr(stream), ws[0], ws[1]))
+    return keys
+
+
+def sort_segmented(keys, seg_offsets, payload=None, stream=None, workspace: Workspace | None = None,
+                   params: Params | None = None):
+    """Sort every segment [off[s], off[s+1]) of keys independently, in place.
+    seg_offsets: device int32/uint32 tensor of S + 1 nondecreasing offsets."""
+    _check_tensors(keys, payload)
+    if not seg_offsets.is_cuda or seg_offsets.element_size() != 4 or seg_offsets.dim() != 1 \
+            or not seg_offsets.is_contiguous():
+        raise ValueError("seg_offsets must be a contiguous 1-D 4-byte device tensor")
+    kb = key_bytes_of(keys)
+    n = keys.shape[0]
+    nseg = seg_offsets.shape[0] - 1
+    if nseg < 0:
+        raise ValueError("seg_offsets needs at least one entry")
+    ws = (None, 0) if workspace is None else (workspace.ptr, workspace.nbytes)
+    pp = None if params is None else ctypes.byref(params.c())
+    _check(lib.binar_sort_ex(_dev_ptr(keys), kb, n, _dev_ptr(payload), _dev_ptr(seg_offsets), nseg, pp,
+                             _stream_ptr(stream), ws[0], ws[1]))
+    return keys
+
+
+def stats(workspace: Workspace | None = None, stream=None) -> dict:
+    """Counters of the last call on `workspace` (None: this device's pool)."""
+    s = _Stats()
+    _check(lib.binar_stats_read(None if workspace is None else workspace.ptr, _stream_ptr(stream),
+                                ctypes.byref(s)))
+    return {"moved": list(s.moved), "hist_keys": list(s.hist_keys), "finish_keys": s.finish_keys,
+            "finish_segments": s.finish_segments, "passes": s.passes, "status": s.status}
+
+
+def default_params(key_bytes: int, has_payload: bool) -> Params:
+    p = _Params()
+    _check(lib.binar_get_default_params(key_bytes, 1 if has_payload else 0, ctypes.byref(p)))
+    return Params(p.digit_bits, p.tile_keys, p.finish_max)
+
+
+def set_default_params(key_bytes: int, has_payload: bool, params: Params) -> None:
+    _check(lib.binar_set_default_params(key_bytes, 1 if has_payload else 0, ctypes.byref(params.c())))

@@ -1,0 +1,435 @@
+// Host side of libbinar.so: argument checks, scratch layout, kernel
+// sequence, the C ABI declared in include/binar.h.
+//
+// Enqueue sequence of one call (all on the caller's stream, no host sync):
+//   k_reset, k_init, then for every possible global pass j < ceil(bits / k):
+//   k_hist, k_plan, k_scatter (each exits at once when its list is empty),
+//   then k_finish for each LDS size class.  The sequence is fixed for a
+//   given (key width, k, n, segment count), so it can be captured in a HIP
+//   graph; the number of passes that do work depends on the data.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "binar.h"
+#include "binar_kernels.h"
+
+namespace binar {
+namespace {
+
+constexpr size_t ALIGN = 256;
+
+size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
+
+// LDS-finish classes: keys per thread of each class, per key width.
+template <int KB>
+struct FinItems;
+template <>
+struct FinItems<4> {
+    static constexpr int v[NCLASS] = {4, 12, 20, 32};
+};
+template <>
+struct FinItems<8> {
+    static constexpr int v[NCLASS] = {4, 12, 20, 32};
+};
+template <>
+struct FinItems<16> {
+    static constexpr int v[NCLASS] = {4, 8, 12, 20};
+};
+
+uint32_t fin_cap(uint32_t kb, int c) {
+    const int *v = (kb == 16) ? FinItems<16>::v : FinItems<4>::v;
+    return (uint32_t)(THREADS * v[c]);
+}
+
+struct Resolved {
+    uint32_t kb, k, tile, T;
+    bool pay;
+};
+
+struct Layout {
+    size_t ctl, list[2], counts[2], bases[2], to_a[2], andor[2], status, fin[NCLASS], keys_b, pay_b, total;
+    uint32_t max_big, max_tiles, max_fin[NCLASS], fin_cap[NCLASS];
+};
+
+binar_params g_defaults[3][2];  // [kb index][has payload]
+std::mutex g_mu;
+
+int kb_index(uint32_t kb) { return kb == 4 ? 0 : (kb == 8 ? 1 : 2); }
+
+bool valid_kb(uint32_t kb) { return kb == 4 || kb == 8 || kb == 16; }
+
+bool supported_k(uint32_t k) { return k == 1 || k == 4 || k == 8; }
+
+bool supported_tile(uint32_t t) { return t == 2048 || t == 4096; }
+
+int resolve(uint32_t kb, bool pay, const binar_params *p, Resolved *r) {
+    binar_params d;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        d = g_defaults[kb_index(kb)][pay ? 1 : 0];
+    }
+    if (p) {
+        if (p->digit_bits) d.digit_bits = p->digit_bits;
+        if (p->tile_keys) d.tile_keys = p->tile_keys;
+        if (p->finish_max) d.finish_max = p->finish_max;
+    }
+    if (!d.digit_bits) d.digit_bits = 8;
+    if (!d.tile_keys) d.tile_keys = 4096;
+    const uint32_t tmax = fin_cap(kb, NCLASS - 1);
+    if (!d.finish_max) d.finish_max = tmax;
+    if (!supported_k(d.digit_bits) || !supported_tile(d.tile_keys)) return BINAR_EINVAL;
+    r->kb = kb;
+    r->k = d.digit_bits;
+    r->tile = d.tile_keys;
+    r->T = std::min(std::max(d.finish_max, 1u), tmax);
+    r->pay = pay;
+    return BINAR_OK;
+}
+
+Layout make_layout(const Resolved &r, uint64_t n) {
+    Layout L{};
+    const uint32_t R = 1u << r.k;
+    L.max_big = (uint32_t)(n / (r.T + 1ull) + 1ull);
+    L.max_tiles = (uint32_t)(n / r.tile + L.max_big + 1ull);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = align_up(off + bytes);
+        return at;
+    };
+    L.ctl = take(sizeof(Ctl));
+    for (int i = 0; i < 2; ++i) {
+        L.list[i] = take((size_t)L.max_big * sizeof(SegEntry));
+        L.counts[i] = take((size_t)L.max_big * R * 4);
+        L.bases[i] = take((size_t)L.max_big * R * 4);
+        L.to_a[i] = take((size_t)L.max_big * R);
+        L.andor[i] = take((size_t)L.max_big * 32);
+    }
+    L.status = take((size_t)L.max_tiles * R * 4);
+    uint32_t prev = 1;
+    for (int c = 0; c < NCLASS; ++c) {
+        L.fin_cap[c] = fin_cap(r.kb, c);
+        L.max_fin[c] = (prev >= r.T) ? 0u : (uint32_t)(n / (prev + 1ull) + 1ull);
+        L.fin[c] = take((size_t)L.max_fin[c] * sizeof(FinEntry));
+        prev = L.fin_cap[c];
+    }
+    L.keys_b = take((size_t)n * r.kb);
+    L.pay_b = take(r.pay ? (size_t)n * 4 : 0);
+    L.total = off;
+    return L;
+}
+
+// ------------------------------------------------------------- device pool
+struct Pool {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+std::mutex g_pool_mu;
+std::vector<Pool> g_pools;
+std::vector<const void *> g_last_ws;  // per device: workspace of the last call
+
+int pool_get(int dev, size_t bytes, void **out) {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    if ((int)g_pools.size() <= dev) g_pools.resize(dev + 1);
+    Pool &p = g_pools[dev];
+    if (p.bytes < bytes) {
+        if (p.ptr) {
+            if (hipDeviceSynchronize() != hipSuccess) return BINAR_EDEVICE;
+            if (hipFree(p.ptr) != hipSuccess) return BINAR_EDEVICE;
+            p.ptr = nullptr;
+            p.bytes = 0;
+        }
+        void *q = nullptr;
+        if (hipMalloc(&q, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return BINAR_ENOMEM;
+        }
+        p.ptr = q;
+        p.bytes = bytes;
+    }
+    *out = p.ptr;
+    return BINAR_OK;
+}
+
+void note_ws(int dev, const void *ws) {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    if ((int)g_last_ws.size() <= dev) g_last_ws.resize(dev + 1, nullptr);
+    g_last_ws[dev] = ws;
+}
+
+// Blocks each kernel keeps resident per CU (cached per kernel).
+struct OccCache {
+    std::mutex mu;
+    std::vector<std::pair<const void *, int>> v;
+    int get(const void *fn) {
+        std::lock_guard<std::mutex> lk(mu);
+        for (auto &e : v)
+            if (e.first == fn) return e.second;
+        int b = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, fn, THREADS, 0) != hipSuccess || b < 1) {
+            (void)hipGetLastError();
+            b = 1;
+        }
+        v.emplace_back(fn, b);
+        return b;
+    }
+} g_occ;
+
+int g_cus = 0;
+int cu_count() {
+    if (!g_cus) {
+        int dev = 0, c = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && c > 0)
+            g_cus = c;
+        else
+            g_cus = 256;
+    }
+    return g_cus;
+}
+
+Work make_work(const Layout &L, const Resolved &r, char *ws, void *keys, uint32_t *pay, uint32_t n_total) {
+    Work w{};
+    w.ctl = reinterpret_cast<Ctl *>(ws + L.ctl);
+    for (int i = 0; i < 2; ++i) {
+        w.list[i] = reinterpret_cast<SegEntry *>(ws + L.list[i]);
+        w.counts[i] = reinterpret_cast<uint32_t *>(ws + L.counts[i]);
+        w.bases[i] = reinterpret_cast<uint32_t *>(ws + L.bases[i]);
+        w.to_a[i] = reinterpret_cast<uint8_t *>(ws + L.to_a[i]);
+        w.andor[i] = reinterpret_cast<unsigned long long *>(ws + L.andor[i]);
+    }
+    w.status = reinterpret_cast<uint32_t *>(ws + L.status);
+    for (int c = 0; c < NCLASS; ++c) {
+        w.fin[c] = reinterpret_cast<FinEntry *>(ws + L.fin[c]);
+        w.fin_cap[c] = L.fin_cap[c];
+        w.max_fin[c] = L.max_fin[c];
+    }
+    w.max_big = L.max_big;
+    w.max_tiles = L.max_tiles;
+    w.finish_max = r.T;
+    w.tile_keys = r.tile;
+    w.n_total = n_total;
+    w.keys[0] = keys;
+    w.keys[1] = ws + L.keys_b;
+    w.pay[0] = pay;
+    w.pay[1] = r.pay ? reinterpret_cast<uint32_t *>(ws + L.pay_b) : nullptr;
+    return w;
+}
+
+template <typename F>
+uint32_t grid_for(F fn, uint32_t work_items) {
+    const uint32_t per_cu = (uint32_t)g_occ.get(reinterpret_cast<const void *>(fn));
+    const uint32_t g = (uint32_t)cu_count() * per_cu;
+    return std::max(1u, std::min(g, work_items));
+}
+
+template <int KB, int K, int ITEMS, bool PAY>
+int enqueue(const Work &w, const Layout &L, const uint32_t *seg_off, uint32_t nseg, uint32_t n,
+            hipStream_t st) {
+    constexpr int R = 1 << K;
+    constexpr int NB = KeyT<KB>::NBITS;
+    constexpr int passes = (NB + K - 1) / K;
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(THREADS), 0, st, w.ctl);
+    const uint32_t ig = std::max(1u, std::min(1024u, (nseg + THREADS - 1) / THREADS));
+    hipLaunchKernelGGL(k_init<R>, dim3(ig), dim3(THREADS), 0, st, w, seg_off, nseg, n, n);
+    const uint32_t hg = grid_for(k_hist<KB, K>, L.max_tiles);
+    const uint32_t pg = std::max(1u, std::min(L.max_big, 1024u));
+    const uint32_t sg = grid_for(k_scatter<KB, K, ITEMS, PAY>, L.max_tiles);
+    for (int j = 0; j < passes; ++j) {
+        const int Lc = j & 1;
+        hipLaunchKernelGGL((k_hist<KB, K>), dim3(hg), dim3(THREADS), 0, st, w, Lc);
+        hipLaunchKernelGGL((k_plan<KB, K>), dim3(pg), dim3(THREADS), 0, st, w, Lc, j);
+        hipLaunchKernelGGL((k_scatter<KB, K, ITEMS, PAY>), dim3(sg), dim3(THREADS), 0, st, w, Lc);
+    }
+    constexpr int I0 = FinItems<KB>::v[0], I1 = FinItems<KB>::v[1], I2 = FinItems<KB>::v[2],
+                  I3 = FinItems<KB>::v[3];
+    if (L.max_fin[0])
+        hipLaunchKernelGGL((k_finish<KB, I0, PAY>), dim3(grid_for(k_finish<KB, I0, PAY>, L.max_fin[0])),
+                           dim3(THREADS), 0, st, w, 0);
+    if (L.max_fin[1])
+        hipLaunchKernelGGL((k_finish<KB, I1, PAY>), dim3(grid_for(k_finish<KB, I1, PAY>, L.max_fin[1])),
+                           dim3(THREADS), 0, st, w, 1);
+    if (L.max_fin[2])
+        hipLaunchKernelGGL((k_finish<KB, I2, PAY>), dim3(grid_for(k_finish<KB, I2, PAY>, L.max_fin[2])),
+                           dim3(THREADS), 0, st, w, 2);
+    if (L.max_fin[3])
+        hipLaunchKernelGGL((k_finish<KB, I3, PAY>), dim3(grid_for(k_finish<KB, I3, PAY>, L.max_fin[3])),
+                           dim3(THREADS), 0, st, w, 3);
+    return hipGetLastError() == hipSuccess ? BINAR_OK : BINAR_EDEVICE;
+}
+
+template <int KB, bool PAY>
+int dispatch_k(const Resolved &r, const Work &w, const Layout &L, const uint32_t *so, uint32_t ns,
+               uint32_t n, hipStream_t st) {
+#define BINAR_CASE(KK, TT)                                      \
+    if (r.k == KK && r.tile == THREADS * TT)                    \
+        return enqueue<KB, KK, TT, PAY>(w, L, so, ns, n, st);
+    BINAR_CASE(8, 16)
+    BINAR_CASE(8, 8)
+    BINAR_CASE(4, 16)
+    BINAR_CASE(4, 8)
+    BINAR_CASE(1, 16)
+    BINAR_CASE(1, 8)
+#undef BINAR_CASE
+    return BINAR_EINVAL;
+}
+
+int dispatch(const Resolved &r, const Work &w, const Layout &L, const uint32_t *so, uint32_t ns, uint32_t n,
+             hipStream_t st) {
+    switch (r.kb) {
+        case 4:
+            return r.pay ? dispatch_k<4, true>(r, w, L, so, ns, n, st) : dispatch_k<4, false>(r, w, L, so, ns, n, st);
+        case 8:
+            return r.pay ? dispatch_k<8, true>(r, w, L, so, ns, n, st) : dispatch_k<8, false>(r, w, L, so, ns, n, st);
+        case 16:
+            return r.pay ? dispatch_k<16, true>(r, w, L, so, ns, n, st)
+                         : dispatch_k<16, false>(r, w, L, so, ns, n, st);
+    }
+    return BINAR_EINVAL;
+}
+
+int run(void *keys, uint32_t kb, uint64_t n, uint32_t *payload, const uint32_t *seg_off, uint32_t nseg,
+        const binar_params *params, hipStream_t st, void *ws, size_t ws_bytes) {
+    if (!valid_kb(kb)) return BINAR_EINVAL;
+    if (n > BINAR_MAX_KEYS) return BINAR_ERANGE;
+    if (seg_off == nullptr && n < 2) return BINAR_OK;  // base case: nothing to order
+    if (seg_off != nullptr && nseg == 0) return BINAR_OK;
+    if (keys == nullptr) return BINAR_EINVAL;
+    if (kb == 16 && (reinterpret_cast<uintptr_t>(keys) & 15u)) return BINAR_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(keys) & 3u) || (reinterpret_cast<uintptr_t>(payload) & 3u))
+        return BINAR_EINVAL;
+    if (kb == 8 && (reinterpret_cast<uintptr_t>(keys) & 7u)) return BINAR_EINVAL;
+    Resolved r;
+    int rc = resolve(kb, payload != nullptr, params, &r);
+    if (rc) return rc;
+    const Layout L = make_layout(r, n);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return BINAR_EDEVICE;
+    if (ws) {
+        if (ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & (ALIGN - 1))) return BINAR_ENOMEM;
+    } else {
+        rc = pool_get(dev, L.total, &ws);
+        if (rc) return rc;
+    }
+    note_ws(dev, ws);
+    const Work w = make_work(L, r, static_cast<char *>(ws), keys, payload, (uint32_t)n);
+    return dispatch(r, w, L, seg_off, seg_off ? nseg : 1u, (uint32_t)n, st);
+}
+
+const void *last_ws(int dev) {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    return (dev < (int)g_last_ws.size()) ? g_last_ws[dev] : nullptr;
+}
+
+}  // namespace
+}  // namespace binar
+
+using namespace binar;
+
+extern "C" {
+
+int binar_sort_ex(void *keys, uint32_t key_bytes, uint64_t n, uint32_t *payload, const uint32_t *seg_offsets,
+                  uint32_t num_segments, const binar_params *params, void *stream, void *workspace,
+                  size_t workspace_bytes) {
+    return run(keys, key_bytes, n, payload, seg_offsets, num_segments, params,
+               static_cast<hipStream_t>(stream), workspace, workspace_bytes);
+}
+
+int binar_sort_async(void *keys, uint32_t key_bytes, uint64_t n, uint32_t *payload, void *stream,
+                     void *workspace, size_t workspace_bytes) {
+    return run(keys, key_bytes, n, payload, nullptr, 0, nullptr, static_cast<hipStream_t>(stream), workspace,
+               workspace_bytes);
+}
+
+int binar_sort_segmented(void *keys, uint32_t key_bytes, const uint32_t *seg_offsets, uint32_t num_segments,
+                         uint64_t n_total, uint32_t *payload, void *stream, void *workspace,
+                         size_t workspace_bytes) {
+    if (seg_offsets == nullptr && num_segments > 0) return BINAR_EINVAL;
+    return run(keys, key_bytes, n_total, payload, seg_offsets, num_segments, nullptr,
+               static_cast<hipStream_t>(stream), workspace, workspace_bytes);
+}
+
+int binar_sort(void *keys, uint32_t key_bytes, uint64_t n, uint32_t *payload) {
+    int rc = run(keys, key_bytes, n, payload, nullptr, 0, nullptr, nullptr, nullptr, 0);
+    if (rc) return rc;
+    if (n < 2) return BINAR_OK;
+    binar_stats st;
+    rc = binar_stats_read(nullptr, nullptr, &st);
+    return rc ? rc : st.status;
+}
+
+size_t binar_workspace_bytes(uint32_t key_bytes, uint64_t n, int has_payload, uint32_t num_segments,
+                             const binar_params *params) {
+    (void)num_segments;
+    if (!valid_kb(key_bytes) || n > BINAR_MAX_KEYS) return 0;
+    Resolved r;
+    if (resolve(key_bytes, has_payload != 0, params, &r)) return 0;
+    return make_layout(r, n).total;
+}
+
+int binar_stats_read(const void *workspace, void *stream, binar_stats *out) {
+    if (!out) return BINAR_EINVAL;
+    std::memset(out, 0, sizeof(*out));
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return BINAR_EDEVICE;
+    const void *ws = workspace ? workspace : last_ws(dev);
+    if (!ws) return BINAR_EINVAL;
+    if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess) return BINAR_EDEVICE;
+    Ctl c;
+    if (hipMemcpy(&c, ws, sizeof(Ctl), hipMemcpyDeviceToHost) != hipSuccess) return BINAR_EDEVICE;
+    for (int j = 0; j < MAX_PASSES; ++j) {
+        out->moved[j] = c.moved[j];
+        out->hist_keys[j] = c.hist_keys[j];
+    }
+    out->finish_keys = c.fin_keys;
+    out->finish_segments = c.fin_segs;
+    out->passes = c.passes;
+    out->status = (c.error & ERR_SEGMENTS) ? BINAR_EINVAL
+                  : ((c.error & ERR_INTERNAL) || c.overflow) ? BINAR_EDEVICE : BINAR_OK;
+    return BINAR_OK;
+}
+
+int binar_get_default_params(uint32_t key_bytes, int has_payload, binar_params *out) {
+    if (!valid_kb(key_bytes) || !out) return BINAR_EINVAL;
+    Resolved r;
+    int rc = resolve(key_bytes, has_payload != 0, nullptr, &r);
+    if (rc) return rc;
+    out->digit_bits = r.k;
+    out->tile_keys = r.tile;
+    out->finish_max = r.T;
+    out->reserved = 0;
+    return BINAR_OK;
+}
+
+int binar_set_default_params(uint32_t key_bytes, int has_payload, const binar_params *p) {
+    if (!valid_kb(key_bytes) || !p) return BINAR_EINVAL;
+    if (p->digit_bits && !supported_k(p->digit_bits)) return BINAR_EINVAL;
+    if (p->tile_keys && !supported_tile(p->tile_keys)) return BINAR_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_defaults[kb_index(key_bytes)][has_payload ? 1 : 0] = *p;
+    return BINAR_OK;
+}
+
+const char *binar_strerror(int status) {
+    switch (status) {
+        case BINAR_OK:
+            return "ok";
+        case BINAR_EINVAL:
+            return "invalid argument (key width, pointer, alignment, tuning knob or segment table)";
+        case BINAR_ERANGE:
+            return "too many keys: the limit is 2^30 - 1";
+        case BINAR_ENOMEM:
+            return "workspace too small or device memory exhausted";
+        case BINAR_EDEVICE:
+            return "HIP runtime error";
+    }
+    return "unknown status";
+}
+
+}  // extern "C"

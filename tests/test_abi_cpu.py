@@ -1,0 +1,75 @@
+"""The C ABI library: it loads, exports every symbol include/binar.h
+declares, and rejects bad arguments before touching a device (no GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "binar.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_0811_3448_amd import binar
+    return binar.lib
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(binar_[a-z_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert "binar_sort" in names and "binar_sort_segmented" in names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_status_strings(lib):
+    from paper_0811_3448_amd import binar
+    for code in (0, -1, -2, -3, -4):
+        assert binar.strerror(code)
+    assert "unknown" in binar.strerror(42)
+
+
+def test_argument_errors_before_device_work(lib):
+    vp = ctypes.c_void_p
+    fake = vp(0x10000)  # never dereferenced: validation fails first
+    assert lib.binar_sort_ex(fake, 3, 100, None, None, 0, None, None, None, 0) == -1   # key width
+    assert lib.binar_sort_ex(fake, 4, 1 << 30, None, None, 0, None, None, None, 0) == -2  # too many
+    assert lib.binar_sort_ex(None, 4, 100, None, None, 0, None, None, None, 0) == -1  # NULL keys
+    assert lib.binar_sort_ex(vp(0x10002), 4, 100, None, None, 0, None, None, None, 0) == -1  # misaligned
+    assert lib.binar_sort_ex(vp(0x10008), 16, 100, None, None, 0, None, None, None, 0) == -1  # 16 B align
+    assert lib.binar_sort_segmented(fake, 4, None, 3, 100, None, None, None, 0) == -1  # NULL table
+    # base cases: nothing to order, no device needed
+    for n in (0, 1):
+        assert lib.binar_sort_ex(None, 4, n, None, None, 0, None, None, None, 0) == 0
+        assert lib.binar_sort(None, 8, n, None) == 0
+    assert lib.binar_sort_segmented(fake, 4, fake, 0, 0, None, None, None, 0) == 0
+
+
+def test_bad_tuning_knobs(lib):
+    from paper_0811_3448_amd import binar
+    bad = binar.Params(digit_bits=3).c()
+    assert lib.binar_sort_ex(ctypes.c_void_p(0x10000), 4, 100, None, None, 0, ctypes.byref(bad),
+                             None, None, 0) == -1
+    with pytest.raises(binar.BinarError):
+        binar.set_default_params(4, True, binar.Params(tile_keys=1000))
+
+
+def test_workspace_bytes(lib):
+    from paper_0811_3448_amd import binar
+    n = 1 << 28
+    wb = binar.workspace_bytes(4, n, True)
+    assert wb >= 8 * n                     # the ping-pong key + payload buffers
+    assert wb < 16 * n                     # plus bounded bookkeeping
+    assert binar.workspace_bytes(4, n, False) < wb
+    assert binar.workspace_bytes(3, 100, True) == 0
+    assert binar.workspace_bytes(4, 1 << 30, True) == 0
+    assert binar.workspace_bytes(16, 1000, True) > binar.workspace_bytes(4, 1000, True)
+    p = binar.default_params(4, True)
+    assert p.digit_bits == 8 and p.tile_keys in (2048, 4096) and p.finish_max > 0

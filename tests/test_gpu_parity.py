@@ -1,0 +1,119 @@
+"""GPU parity: libbinar.so (through the C ABI) against the CPU oracle,
+element by element, keys and permutation bit-exact."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_util import gpu_sort, gpu_sort_segmented, need_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def iota(n):
+    return np.arange(n, dtype=np.uint32)
+
+
+def P(k=0, tile=0, T=0):
+    from paper_0811_3448_amd import Params
+    return Params(digit_bits=k, tile_keys=tile, finish_max=T)
+
+
+def compare(keys, with_payload=True, params=None):
+    n = keys.shape[0]
+    pay = iota(n) if with_payload else None
+    print("case n=%d kb=%d payload=%s params=%s" % (n, oracle.key_bytes_of(keys), with_payload, params),
+          flush=True)
+    gk, gp = gpu_sort(keys, pay, params=params)
+    rk, rp = oracle.sort(keys, pay)
+    assert np.array_equal(gk, rk), "keys differ"
+    if with_payload:
+        assert np.array_equal(gp, rp), "permutation differs"
+
+
+EDGE = [0, 1, 0x7FFFFFFF, 0x80000000, 0xFFFFFFFF, 0x80000001, 0x00010000, 0xFF]
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 64, 65, 1000, 8192, 8193, 50_000])
+def test_u32_uniform_sizes(n):
+    compare(workloads.u32_uniform(n, 1000 + n))
+
+
+def test_u32_keys_only_2e16():
+    compare(workloads.single_keys("u32_2e16_uniform_keys"), with_payload=False)
+
+
+@pytest.mark.parametrize("dist", ["and4", "dup256", "edge", "equal", "sorted", "reversed"])
+def test_u32_distributions(dist):
+    n = 300_000
+    keys = {"and4": lambda: workloads.u32_and4(n, 7),
+            "dup256": lambda: workloads.u32_dup(n, 8, 256),
+            "edge": lambda: workloads.small_alphabet_u32(n, 9, EDGE),
+            "equal": lambda: np.full(n, 0x12345678, dtype=np.uint32),
+            "sorted": lambda: np.sort(workloads.u32_uniform(n, 10)),
+            "reversed": lambda: np.sort(workloads.u32_uniform(n, 11))[::-1].copy()}[dist]()
+    compare(keys)
+
+
+@pytest.mark.parametrize("k,tile,T", [(8, 4096, 64), (8, 2048, 300), (4, 4096, 100), (4, 2048, 1000),
+                                      (1, 4096, 64), (1, 2048, 5000), (8, 4096, 1)])
+def test_u32_global_passes(k, tile, T):
+    """Small LDS threshold: many tiles per segment, several global passes,
+    look-back across tiles, ragged last tiles."""
+    n = 100_003
+    compare(workloads.u32_uniform(n, 20 + k), params=P(k, tile, T))
+    compare(workloads.u32_and4(n, 21 + k), params=P(k, tile, T))
+    compare(workloads.u32_dup(n, 22 + k, 256), params=P(k, tile, T))
+
+
+@pytest.mark.parametrize("dist", ["uniform", "nearly", "zipf", "dup"])
+@pytest.mark.parametrize("T", [0, 200])
+def test_u64(dist, T):
+    n = 200_001
+    keys = {"uniform": lambda: workloads.u64_uniform(n, 31),
+            "nearly": lambda: workloads.u64_nearly_sorted(n, 32, 0.01),
+            "zipf": lambda: workloads.u64_zipf(n, 33, 1 << 12, 1.1),
+            "dup": lambda: workloads.u64_uniform(16, 34)[workloads.below(n, 35, 16).astype(np.int64)]}[dist]()
+    compare(keys, params=P(T=T))
+
+
+@pytest.mark.parametrize("prefix", [0, 5, 12, 16])
+@pytest.mark.parametrize("T", [0, 100])
+def test_str16(prefix, T):
+    n = 60_000
+    compare(workloads.str16(n, 40 + prefix, prefix), params=P(T=T))
+
+
+@pytest.mark.parametrize("kb", [4, 8, 16])
+def test_keys_only_widths(kb):
+    n = 77_777
+    keys = {4: lambda: workloads.u32_uniform(n, 51), 8: lambda: workloads.u64_uniform(n, 52),
+            16: lambda: workloads.str16(n, 53, 3)}[kb]()
+    compare(keys, with_payload=False, params=P(T=500))
+
+
+def test_determinism():
+    keys = workloads.u32_and4(500_000, 61)
+    a = gpu_sort(keys, iota(keys.shape[0]))
+    b = gpu_sort(keys, iota(keys.shape[0]))
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("T", [0, 50])
+def test_segmented_small(T):
+    keys, off = workloads.batched_u32(300, seed=71, median=200, sigma=1.2, max_len=20_000)
+    off = off.copy()
+    off[10] = off[9]            # empty segment
+    off[20] = off[19] + 1       # one-key segment
+    off = np.maximum.accumulate(off)
+    n = keys.shape[0]
+    print("segmented n=%d S=%d T=%d" % (n, 300, T), flush=True)
+    gk, gp = gpu_sort_segmented(keys, off, iota(n), params=P(T=T))
+    rk, rp = oracle.sort_segmented(keys, off, iota(n))
+    assert np.array_equal(gk, rk)
+    assert np.array_equal(gp, rp)
