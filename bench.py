@@ -1,0 +1,219 @@
+#!/usr/bin/env python3
+"""Benchmark of the gfx950 stable binar sort on one MI355X.
+
+One step = one complete sort (every global pass + the LDS finish) of one
+batch of 2^28 uniform uint32 keys carrying a uint32 index payload, already
+resident in HBM.  Each step sorts its own unsorted copy (prepared before the
+timed region), so no step sorts sorted data.
+
+Prints ONE JSON line: Gkeys/s over the timed steps, the roofline of the
+kernel that takes the most time (algorithmic bytes / its average launch time,
+from HIP events recorded on the kernel's own stream inside the timed
+region), and the CPU oracle timed on a bounded sample on one host core.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Gkeys/s and % HBM peak, 2^28 uint32+u32 payload; p50/p99 batched-serve latency"
+HBM_PEAK_GBS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
+CSRC = os.path.join(ROOT, "paper_0811_3448_amd", "csrc")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they
+    were taken on the current kernel sources (else None)."""
+    path = os.path.join(PROFILES, "traffic_%s_%s.json" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("source_sha256") != kernel_source_hash():
+        return None
+    return t.get("traffic_bytes_per_launch")
+
+
+def cpu_baseline(keys_np, log2_sample: int):
+    import numpy as np
+    import oracle
+    n = min(keys_np.shape[0], 1 << log2_sample)
+    k = keys_np[:n].copy()
+    p = np.arange(n, dtype=np.uint32)
+    oracle.build()
+    t0 = time.perf_counter()
+    oracle.sort(k, p)
+    dt = time.perf_counter() - t0
+    return {"value": n / dt / 1e9, "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
+            "sample": "first 2^%d keys (+ index payload) of the same workload, recursive stable binar "
+                      "partition in C on one host core, %.1f s" % (log2_sample, dt)}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="u32_2e28_uniform")
+    ap.add_argument("--cpu-sample-log2", type=int, default=25)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--digit-bits", type=int, default=0)
+    ap.add_argument("--tile-keys", type=int, default=0)
+    ap.add_argument("--finish-max", type=int, default=0)
+    ap.add_argument("--offsets", type=int, default=0, help="1 = chunk prefixes, 2 = decoupled look-back")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the sort runs on a single MI355X and has no "
+              "multi-GPU path; run it with --gpus 1", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    lib_path = os.path.join(ROOT, "paper_0811_3448_amd", "libbinar.so")
+    if not os.path.exists(lib_path):
+        sys.path.insert(0, os.path.join(ROOT, "paper_0811_3448_amd"))
+        import build as _b  # noqa: E402
+        _b.build()
+    import paper_0811_3448_amd as binar
+    import workloads
+
+    name = args.workload
+    kb, n, has_pay, desc = workloads.SINGLE[name]
+    print("bench: generating %s (%s)" % (name, desc), file=sys.stderr, flush=True)
+    keys_np = workloads.single_keys(name)
+    if kb == 4:
+        keys_t = torch.from_numpy(keys_np.view(np.int32))
+    else:
+        keys_t = torch.from_numpy(keys_np.view(np.int64))
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    pristine = keys_t.to(dev)
+    pay0 = torch.arange(n, dtype=torch.int32, device=dev) if has_pay else None
+    K, W = args.steps, args.warmup
+    bufs = [(pristine.clone(), None if pay0 is None else pay0.clone()) for _ in range(K + W)]
+    params = binar.Params(args.digit_bits, args.tile_keys, args.finish_max, args.offsets)
+    ws = binar.Workspace(binar.workspace_bytes(kb, n, has_pay, 1, params), device=dev)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+
+    print("bench: warmup %d" % W, file=sys.stderr, flush=True)
+    for i in range(W):
+        binar.sort(bufs[i][0], bufs[i][1], workspace=ws, params=params)
+    torch.cuda.synchronize()
+    st = binar.stats(ws)
+    if st["status"] != 0:
+        raise RuntimeError("sort reported status %d" % st["status"])
+
+    print("bench: timing %d steps" % K, file=sys.stderr, flush=True)
+    binar.profile_enable(True)
+    binar.profile_read()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for i in range(W, W + K):
+        binar.sort(bufs[i][0], bufs[i][1], workspace=ws, params=params)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launches = binar.profile_read()
+    binar.profile_enable(False)
+    gpu_ms = ev0.elapsed_time(ev1)
+    st = binar.stats(ws)
+    if st["status"] != 0:
+        raise RuntimeError("sort reported status %d" % st["status"])
+
+    # the last sorted batch must be sorted (unsigned order) -- a cheap sanity check
+    last = bufs[-1][0]
+    if kb == 4:
+        u = last.to(torch.int64) & 0xFFFFFFFF
+        ok = bool((u[1:] >= u[:-1]).all().item())
+    else:
+        s = last ^ (-(1 << 63))
+        ok = bool((s[1:] >= s[:-1]).all().item())
+    if not ok:
+        raise RuntimeError("output not sorted")
+
+    # algorithmic bytes per sort, per kernel kind (exact counters from the device)
+    pb = 4 if has_pay else 0
+    per_kernel = {"k_hist": sum(kb * x for x in st["hist_keys"]),
+                  "k_scatter": sum(2 * (kb + pb) * x for x in st["moved"])}
+    for c in range(4):
+        per_kernel["k_finish%d" % c] = 2 * (kb + pb) * st["finish_class_keys"][c]
+    total_bytes = sum(per_kernel.values())
+
+    agg = {}
+    for nm, _pass, ms in launches:
+        a = agg.setdefault(nm, [0.0, 0])
+        a[0] += ms
+        a[1] += 1
+    ranked = sorted(((v[0], nm) for nm, v in agg.items() if per_kernel.get(nm, 0) > 0), reverse=True)
+    dom = ranked[0][1]
+    dom_ms, dom_launches = agg[dom]
+    bytes_per_launch = per_kernel[dom] * K / dom_launches
+    avg_ms = dom_ms / dom_launches
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+
+    ms_per_step = gpu_ms / K
+    value = n * K / (gpu_ms * 1e-3) / 1e9
+    result = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Gkeys/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32" if kb == 4 else ("u64" if kb == 8 else "u8x16"),
+        "data": "synthetic",
+        "config": {"workload": "%s: %s" % (name, desc), "n": n, "key_bytes": kb, "payload_bytes": pb,
+                   "digit_bits": binar.default_params(kb, has_pay).digit_bits if not args.digit_bits
+                   else args.digit_bits,
+                   "tile_keys": args.tile_keys or binar.default_params(kb, has_pay).tile_keys,
+                   "finish_max": args.finish_max or binar.default_params(kb, has_pay).finish_max,
+                   "offsets": "decoupled look-back" if args.offsets == 2 else "chunk prefixes",
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(dom, name),
+                     "bytes_per_launch": int(bytes_per_launch), "avg_launch_ms": round(avg_ms, 4),
+                     "launches_per_step": dom_launches // K},
+        "sort_roofline": {"algorithmic_bytes_per_step": int(total_bytes),
+                          "achieved_gbs": round(total_bytes / (ms_per_step * 1e-3) / 1e9, 1),
+                          "frac": round(total_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "kernels_ms_per_step": {nm: round(v[0] / K, 4) for nm, v in sorted(agg.items())},
+        "passes": st["passes"],
+        "moved_per_pass": [x for x in st["moved"] if x],
+        "wall_s": round(wall, 4),
+    }
+    if not args.no_cpu_baseline:
+        print("bench: CPU oracle sample", file=sys.stderr, flush=True)
+        result["cpu_baseline"] = cpu_baseline(keys_np, args.cpu_sample_log2)
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -66,16 +66,29 @@ extern "C" {
 #define BINAR_MAX_KEYS ((1u << 30) - 1u)
 
 /* Tuning knobs; a zero field means "library default".
- *   digit_bits : bits taken per global pass, 1..8 (1 = the paper's binary
- *                partition step, made stable).
- *   tile_keys  : keys per scatter tile, one of 2048, 4096, 8192.
+ *   digit_bits : bits taken per global pass: 1, 4 or 8 (1 = the paper's
+ *                binary partition step, made stable).
+ *   tile_keys  : keys per scatter tile: 2048, 4096 or (digit_bits 8) 8192.
  *   finish_max : largest sub-array finished in on-chip memory (LDS) by one
- *                workgroup; capped by the key width's largest LDS class. */
+ *                workgroup; capped by the key width's largest LDS class.
+ *   offsets    : how a scatter tile finds where its keys go:
+ *                1 = per-chunk counts from the digit-count pass, scanned
+ *                    once per segment; each block then walks its chunk of
+ *                    tiles in order (no waits between blocks);
+ *                2 = decoupled look-back over the segment's earlier tiles
+ *                    (tiles taken in ticket order).
+ *                0 = default (1).
+ *   key_bits   : sort by the leading key_bits bits of each key only (1 ..
+ *                8 * key_bytes; 0 = all): keys equal in those bits keep
+ *                their input order.  This is the state the method reaches
+ *                after partitioning on the first key_bits bits. */
 typedef struct binar_params {
     uint32_t digit_bits;
     uint32_t tile_keys;
     uint32_t finish_max;
-    uint32_t reserved;
+    uint32_t offsets;
+    uint32_t key_bits;
+    uint32_t reserved[3];
 } binar_params;
 
 /* Counters of the last call that used a workspace (exact integers).
@@ -91,7 +104,17 @@ typedef struct binar_stats {
     uint64_t finish_segments;
     uint32_t passes;
     int32_t status;
+    uint64_t finish_class_keys[4];     /* finish_keys split by LDS size class */
+    uint64_t finish_class_segments[4];
+    uint64_t copyback_keys;            /* finished keys copied from scratch to the caller's buffer */
 } binar_stats;
+
+/* One timed kernel launch (see binar_profile_enable). */
+typedef struct binar_launch_time {
+    char name[32];   /* "k_hist", "k_plan", "k_scatter", "k_finish0".."k_finish3", ... */
+    int32_t pass;    /* global pass index, -1 for launches outside the pass loop */
+    float ms;        /* elapsed time between the events around the launch */
+} binar_launch_time;
 
 /* Sort n keys (and payload, may be NULL) on the null stream with the pool;
  * blocks until the sort has finished. */
@@ -129,6 +152,14 @@ int binar_stats_read(const void *workspace, void *stream, binar_stats *out);
 /* The defaults binar_sort uses; set by the autotuner.  key_bytes 4, 8, 16. */
 int binar_get_default_params(uint32_t key_bytes, int has_payload, binar_params *out);
 int binar_set_default_params(uint32_t key_bytes, int has_payload, const binar_params *p);
+
+/* Launch timing for measurement.  While enabled (on = 1), every kernel the
+ * library enqueues is bracketed by two HIP events recorded on the same
+ * stream as the kernel.  binar_profile_read waits for the recorded events,
+ * copies up to `cap` records (oldest first) to `out`, sets *count to the
+ * number copied and clears the log.  Disabling drops unread records. */
+int binar_profile_enable(int on);
+int binar_profile_read(binar_launch_time *out, uint32_t cap, uint32_t *count);
 
 /* Static description of a status code. */
 const char *binar_strerror(int status);

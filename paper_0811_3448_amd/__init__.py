@@ -15,6 +15,8 @@ from .binar import (  # noqa: F401
     default_params,
     key_bytes_of,
     lib,
+    profile_enable,
+    profile_read,
     set_default_params,
     sort,
     sort_segmented,

@@ -1,6 +1,6 @@
 """ctypes binding of libbinar.so (argument marshalling only).
 
-The library must have been built (``python -m paper_0811_3448_amd.build``);
+The library must have been built (``python paper_0811_3448_amd/build.py``);
 importing this module without it raises ImportError -- there is no fallback.
 """
 from __future__ import annotations
@@ -18,18 +18,25 @@ MAX_KEYS = (1 << 30) - 1
 
 class _Params(ctypes.Structure):
     _fields_ = [("digit_bits", ctypes.c_uint32), ("tile_keys", ctypes.c_uint32),
-                ("finish_max", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("finish_max", ctypes.c_uint32), ("offsets", ctypes.c_uint32),
+                ("key_bits", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 3)]
 
 
 class _Stats(ctypes.Structure):
     _fields_ = [("moved", ctypes.c_uint64 * 16), ("hist_keys", ctypes.c_uint64 * 16),
                 ("finish_keys", ctypes.c_uint64), ("finish_segments", ctypes.c_uint64),
-                ("passes", ctypes.c_uint32), ("status", ctypes.c_int32)]
+                ("passes", ctypes.c_uint32), ("status", ctypes.c_int32),
+                ("finish_class_keys", ctypes.c_uint64 * 4), ("finish_class_segments", ctypes.c_uint64 * 4),
+                ("copyback_keys", ctypes.c_uint64)]
+
+
+class _LaunchTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("pass_", ctypes.c_int32), ("ms", ctypes.c_float)]
 
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError("libbinar.so is not built (%s); run python -m paper_0811_3448_amd.build" % LIB_PATH)
+        raise ImportError("libbinar.so is not built (%s); run python paper_0811_3448_amd/build.py" % LIB_PATH)
     L = ctypes.CDLL(LIB_PATH)
     vp, u32, u64, sz, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t, ctypes.c_int
     P = ctypes.POINTER(_Params)
@@ -42,10 +49,13 @@ def _load():
     L.binar_stats_read.argtypes = [vp, vp, ctypes.POINTER(_Stats)]
     L.binar_get_default_params.argtypes = [u32, i32, P]
     L.binar_set_default_params.argtypes = [u32, i32, P]
+    L.binar_profile_enable.argtypes = [i32]
+    L.binar_profile_read.argtypes = [ctypes.POINTER(_LaunchTime), u32, ctypes.POINTER(u32)]
     L.binar_strerror.argtypes = [i32]
     L.binar_strerror.restype = ctypes.c_char_p
     for f in ("binar_sort", "binar_sort_async", "binar_sort_segmented", "binar_sort_ex",
-              "binar_stats_read", "binar_get_default_params", "binar_set_default_params"):
+              "binar_stats_read", "binar_get_default_params", "binar_set_default_params",
+              "binar_profile_enable", "binar_profile_read"):
         getattr(L, f).restype = i32
     return L
 
@@ -68,14 +78,20 @@ def _check(rc: int) -> None:
         raise BinarError(rc)
 
 
+OFFSETS_CHUNKED, OFFSETS_LOOKBACK = 1, 2
+
+
 @dataclass
 class Params:
+    """Tuning knobs (0 = library default); see binar_params in binar.h."""
     digit_bits: int = 0
     tile_keys: int = 0
     finish_max: int = 0
+    offsets: int = 0
+    key_bits: int = 0
 
     def c(self):
-        return _Params(self.digit_bits, self.tile_keys, self.finish_max, 0)
+        return _Params(self.digit_bits, self.tile_keys, self.finish_max, self.offsets, self.key_bits)
 
 
 def key_bytes_of(keys) -> int:
@@ -167,13 +183,28 @@ def stats(workspace: Workspace | None = None, stream=None) -> dict:
     _check(lib.binar_stats_read(None if workspace is None else workspace.ptr, _stream_ptr(stream),
                                 ctypes.byref(s)))
     return {"moved": list(s.moved), "hist_keys": list(s.hist_keys), "finish_keys": s.finish_keys,
-            "finish_segments": s.finish_segments, "passes": s.passes, "status": s.status}
+            "finish_segments": s.finish_segments, "passes": s.passes, "status": s.status,
+            "finish_class_keys": list(s.finish_class_keys),
+            "finish_class_segments": list(s.finish_class_segments), "copyback_keys": s.copyback_keys}
+
+
+def profile_enable(on: bool = True) -> None:
+    """Bracket every library kernel launch with HIP events on its stream."""
+    _check(lib.binar_profile_enable(1 if on else 0))
+
+
+def profile_read(cap: int = 1 << 16) -> list:
+    """[(name, pass, ms)] of the launches timed since the last read."""
+    buf = (_LaunchTime * cap)()
+    cnt = ctypes.c_uint32(0)
+    _check(lib.binar_profile_read(buf, cap, ctypes.byref(cnt)))
+    return [(buf[i].name.decode(), buf[i].pass_, float(buf[i].ms)) for i in range(cnt.value)]
 
 
 def default_params(key_bytes: int, has_payload: bool) -> Params:
     p = _Params()
     _check(lib.binar_get_default_params(key_bytes, 1 if has_payload else 0, ctypes.byref(p)))
-    return Params(p.digit_bits, p.tile_keys, p.finish_max)
+    return Params(p.digit_bits, p.tile_keys, p.finish_max, p.offsets)
 
 
 def set_default_params(key_bytes: int, has_payload: bool, params: Params) -> None:

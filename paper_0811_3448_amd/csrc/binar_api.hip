@@ -26,7 +26,9 @@ constexpr size_t ALIGN = 256;
 
 size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
 
-// LDS-finish classes: keys per thread of each class, per key width.
+// LDS-finish classes: a block of FIN_BT threads, keys per thread of each
+// class, per key width (largest class: 8192 keys, 5120 for 16-byte keys).
+constexpr int FIN_BT = 256;
 template <int KB>
 struct FinItems;
 template <>
@@ -44,17 +46,34 @@ struct FinItems<16> {
 
 uint32_t fin_cap(uint32_t kb, int c) {
     const int *v = (kb == 16) ? FinItems<16>::v : FinItems<4>::v;
-    return (uint32_t)(THREADS * v[c]);
+    return (uint32_t)(FIN_BT * v[c]);
 }
 
+// Scatter tiles: (threads per block, keys per thread) per tile size.
+template <int TILE>
+struct ScatterShape;
+template <>
+struct ScatterShape<2048> {
+    static constexpr int BT = 256, ITEMS = 8;
+};
+template <>
+struct ScatterShape<4096> {
+    static constexpr int BT = 512, ITEMS = 8;
+};
+template <>
+struct ScatterShape<8192> {
+    static constexpr int BT = 1024, ITEMS = 8;
+};
+
 struct Resolved {
-    uint32_t kb, k, tile, T;
+    uint32_t kb, k, tile, T, nbits;
     bool pay;
+    bool lookback;
 };
 
 struct Layout {
-    size_t ctl, list[2], counts[2], bases[2], to_a[2], andor[2], status, fin[NCLASS], keys_b, pay_b, total;
-    uint32_t max_big, max_tiles, max_fin[NCLASS], fin_cap[NCLASS];
+    size_t ctl, list[2], counts[2], bases[2], andor[2], pcnt, status, fin[NCLASS], cpy, keys_b, pay_b, total;
+    uint32_t max_big, max_tiles, max_fin[NCLASS], fin_cap[NCLASS], max_cpy;
 };
 
 binar_params g_defaults[3][2];  // [kb index][has payload]
@@ -66,7 +85,7 @@ bool valid_kb(uint32_t kb) { return kb == 4 || kb == 8 || kb == 16; }
 
 bool supported_k(uint32_t k) { return k == 1 || k == 4 || k == 8; }
 
-bool supported_tile(uint32_t t) { return t == 2048 || t == 4096; }
+bool supported_tile(uint32_t t) { return t == 2048 || t == 4096 || t == 8192; }
 
 int resolve(uint32_t kb, bool pay, const binar_params *p, Resolved *r) {
     binar_params d;
@@ -78,17 +97,23 @@ int resolve(uint32_t kb, bool pay, const binar_params *p, Resolved *r) {
         if (p->digit_bits) d.digit_bits = p->digit_bits;
         if (p->tile_keys) d.tile_keys = p->tile_keys;
         if (p->finish_max) d.finish_max = p->finish_max;
+        if (p->offsets) d.offsets = p->offsets;
     }
     if (!d.digit_bits) d.digit_bits = 8;
     if (!d.tile_keys) d.tile_keys = 4096;
+    if (!d.offsets) d.offsets = 1;
     const uint32_t tmax = fin_cap(kb, NCLASS - 1);
     if (!d.finish_max) d.finish_max = tmax;
-    if (!supported_k(d.digit_bits) || !supported_tile(d.tile_keys)) return BINAR_EINVAL;
+    if (!supported_k(d.digit_bits) || !supported_tile(d.tile_keys) || d.offsets > 2) return BINAR_EINVAL;
+    const uint32_t nbits = (p && p->key_bits) ? p->key_bits : 8u * kb;
+    if (nbits > 8u * kb) return BINAR_EINVAL;
+    r->nbits = nbits;
     r->kb = kb;
     r->k = d.digit_bits;
     r->tile = d.tile_keys;
     r->T = std::min(std::max(d.finish_max, 1u), tmax);
     r->pay = pay;
+    r->lookback = d.offsets == 2;
     return BINAR_OK;
 }
 
@@ -108,10 +133,10 @@ Layout make_layout(const Resolved &r, uint64_t n) {
         L.list[i] = take((size_t)L.max_big * sizeof(SegEntry));
         L.counts[i] = take((size_t)L.max_big * R * 4);
         L.bases[i] = take((size_t)L.max_big * R * 4);
-        L.to_a[i] = take((size_t)L.max_big * R);
         L.andor[i] = take((size_t)L.max_big * 32);
     }
-    L.status = take((size_t)L.max_tiles * R * 4);
+    L.pcnt = take((size_t)L.max_tiles * R * 4);
+    L.status = take(r.lookback ? (size_t)L.max_tiles * R * 4 : 0);
     uint32_t prev = 1;
     for (int c = 0; c < NCLASS; ++c) {
         L.fin_cap[c] = fin_cap(r.kb, c);
@@ -119,6 +144,10 @@ Layout make_layout(const Resolved &r, uint64_t n) {
         L.fin[c] = take((size_t)L.max_fin[c] * sizeof(FinEntry));
         prev = L.fin_cap[c];
     }
+    // copy-back runs: each is bounded by a child that is not finished (two
+    // or more keys) or by its parent's end
+    L.max_cpy = (uint32_t)(n / 2 + L.max_big + 2);
+    L.cpy = take((size_t)L.max_cpy * sizeof(CopyEntry));
     L.keys_b = take((size_t)n * r.kb);
     L.pay_b = take(r.pay ? (size_t)n * 4 : 0);
     L.total = off;
@@ -167,12 +196,12 @@ void note_ws(int dev, const void *ws) {
 struct OccCache {
     std::mutex mu;
     std::vector<std::pair<const void *, int>> v;
-    int get(const void *fn) {
+    int get(const void *fn, int block) {
         std::lock_guard<std::mutex> lk(mu);
         for (auto &e : v)
             if (e.first == fn) return e.second;
         int b = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, fn, THREADS, 0) != hipSuccess || b < 1) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, fn, block, 0) != hipSuccess || b < 1) {
             (void)hipGetLastError();
             b = 1;
         }
@@ -201,19 +230,22 @@ Work make_work(const Layout &L, const Resolved &r, char *ws, void *keys, uint32_
         w.list[i] = reinterpret_cast<SegEntry *>(ws + L.list[i]);
         w.counts[i] = reinterpret_cast<uint32_t *>(ws + L.counts[i]);
         w.bases[i] = reinterpret_cast<uint32_t *>(ws + L.bases[i]);
-        w.to_a[i] = reinterpret_cast<uint8_t *>(ws + L.to_a[i]);
         w.andor[i] = reinterpret_cast<unsigned long long *>(ws + L.andor[i]);
     }
+    w.pcnt = reinterpret_cast<uint32_t *>(ws + L.pcnt);
     w.status = reinterpret_cast<uint32_t *>(ws + L.status);
     for (int c = 0; c < NCLASS; ++c) {
         w.fin[c] = reinterpret_cast<FinEntry *>(ws + L.fin[c]);
         w.fin_cap[c] = L.fin_cap[c];
         w.max_fin[c] = L.max_fin[c];
     }
+    w.cpy = reinterpret_cast<CopyEntry *>(ws + L.cpy);
+    w.max_cpy = L.max_cpy;
     w.max_big = L.max_big;
     w.max_tiles = L.max_tiles;
     w.finish_max = r.T;
     w.tile_keys = r.tile;
+    w.nbits = r.nbits;
     w.n_total = n_total;
     w.keys[0] = keys;
     w.keys[1] = ws + L.keys_b;
@@ -222,60 +254,155 @@ Work make_work(const Layout &L, const Resolved &r, char *ws, void *keys, uint32_
     return w;
 }
 
+// ---------------------------------------------------------------- profiler
+// Optional launch timing: an event pair on the launch stream around every
+// kernel, read back by binar_profile_read.
+struct Prof {
+    std::mutex mu;
+    bool on = false;
+    struct Rec {
+        hipEvent_t a, b;
+        char name[32];
+        int pass;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> spare;
+
+    hipEvent_t ev() {
+        if (!spare.empty()) {
+            hipEvent_t e = spare.back();
+            spare.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+} g_prof;
+
+struct Timed {
+    hipStream_t st;
+    hipEvent_t a = nullptr, b = nullptr;
+    const char *name;
+    int pass;
+    Timed(hipStream_t s, const char *n, int p) : st(s), name(n), pass(p) {
+        std::lock_guard<std::mutex> lk(g_prof.mu);
+        if (!g_prof.on) return;
+        a = g_prof.ev();
+        b = g_prof.ev();
+        if (a && b) (void)hipEventRecord(a, st);
+    }
+    ~Timed() {
+        std::lock_guard<std::mutex> lk(g_prof.mu);
+        if (!a || !b) return;
+        (void)hipEventRecord(b, st);
+        Prof::Rec r;
+        r.a = a;
+        r.b = b;
+        std::snprintf(r.name, sizeof(r.name), "%s", name);
+        r.pass = pass;
+        g_prof.recs.push_back(r);
+    }
+};
+
 template <typename F>
-uint32_t grid_for(F fn, uint32_t work_items) {
-    const uint32_t per_cu = (uint32_t)g_occ.get(reinterpret_cast<const void *>(fn));
+uint32_t grid_for(F fn, uint32_t work_items, int block = THREADS) {
+    const uint32_t per_cu = (uint32_t)g_occ.get(reinterpret_cast<const void *>(fn), block);
     const uint32_t g = (uint32_t)cu_count() * per_cu;
     return std::max(1u, std::min(g, work_items));
 }
 
-template <int KB, int K, int ITEMS, bool PAY>
-int enqueue(const Work &w, const Layout &L, const uint32_t *seg_off, uint32_t nseg, uint32_t n,
-            hipStream_t st) {
+template <int KB, int K, int TILE, bool PAY, bool LB>
+int enqueue(Work w, const Layout &L, const uint32_t *seg_off, uint32_t nseg, uint32_t n, hipStream_t st) {
+    constexpr int SBT = ScatterShape<TILE>::BT, SIT = ScatterShape<TILE>::ITEMS;
     constexpr int R = 1 << K;
-    constexpr int NB = KeyT<KB>::NBITS;
-    constexpr int passes = (NB + K - 1) / K;
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(THREADS), 0, st, w.ctl);
+    const int passes = ((int)w.nbits + K - 1) / K;
+    {
+        Timed tm(st, "k_reset", -1);
+        hipLaunchKernelGGL(k_reset, dim3(1), dim3(THREADS), 0, st, w.ctl);
+    }
     const uint32_t ig = std::max(1u, std::min(1024u, (nseg + THREADS - 1) / THREADS));
-    hipLaunchKernelGGL(k_init<R>, dim3(ig), dim3(THREADS), 0, st, w, seg_off, nseg, n, n);
-    const uint32_t hg = grid_for(k_hist<KB, K>, L.max_tiles);
+    {
+        Timed tm(st, "k_init", -1);
+        hipLaunchKernelGGL(k_init<R>, dim3(ig), dim3(THREADS), 0, st, w, seg_off, nseg, n, n);
+    }
+    // the chunked scatter and the digit count share one grid: it fixes the
+    // pieces whose prefixes k_pscan computes
+    const uint32_t sg = grid_for(k_scatter<KB, K, SBT, SIT, PAY, LB>, L.max_tiles, SBT);
+    w.chunk_grid = sg;
+    const uint32_t hg = sg;
     const uint32_t pg = std::max(1u, std::min(L.max_big, 1024u));
-    const uint32_t sg = grid_for(k_scatter<KB, K, ITEMS, PAY>, L.max_tiles);
+    constexpr uint32_t NG = (R < 32) ? 1u : (uint32_t)R / 32u;
+    const uint32_t qg = std::max(1u, std::min(L.max_big * NG, 2048u));
     for (int j = 0; j < passes; ++j) {
         const int Lc = j & 1;
-        hipLaunchKernelGGL((k_hist<KB, K>), dim3(hg), dim3(THREADS), 0, st, w, Lc);
-        hipLaunchKernelGGL((k_plan<KB, K>), dim3(pg), dim3(THREADS), 0, st, w, Lc, j);
-        hipLaunchKernelGGL((k_scatter<KB, K, ITEMS, PAY>), dim3(sg), dim3(THREADS), 0, st, w, Lc);
+        {
+            Timed tm(st, "k_hist", j);
+            hipLaunchKernelGGL((k_hist<KB, K, LB>), dim3(hg), dim3(THREADS), 0, st, w, Lc);
+        }
+        {
+            Timed tm(st, "k_pscan", j);
+            hipLaunchKernelGGL((k_pscan<K>), dim3(qg), dim3(THREADS), 0, st, w, Lc);
+        }
+        {
+            Timed tm(st, "k_plan", j);
+            hipLaunchKernelGGL((k_plan<KB, K>), dim3(pg), dim3(THREADS), 0, st, w, Lc, j);
+        }
+        {
+            Timed tm(st, "k_scatter", j);
+            hipLaunchKernelGGL((k_scatter<KB, K, SBT, SIT, PAY, LB>), dim3(sg), dim3(SBT), 0, st, w, Lc);
+        }
+    }
+    {
+        Timed tm(st, "k_copyback", -1);
+        hipLaunchKernelGGL((k_copyback<KB, PAY>), dim3(grid_for(k_copyback<KB, PAY>, L.max_cpy)), dim3(THREADS), 0,
+                           st, w);
     }
     constexpr int I0 = FinItems<KB>::v[0], I1 = FinItems<KB>::v[1], I2 = FinItems<KB>::v[2],
                   I3 = FinItems<KB>::v[3];
-    if (L.max_fin[0])
-        hipLaunchKernelGGL((k_finish<KB, I0, PAY>), dim3(grid_for(k_finish<KB, I0, PAY>, L.max_fin[0])),
-                           dim3(THREADS), 0, st, w, 0);
-    if (L.max_fin[1])
-        hipLaunchKernelGGL((k_finish<KB, I1, PAY>), dim3(grid_for(k_finish<KB, I1, PAY>, L.max_fin[1])),
-                           dim3(THREADS), 0, st, w, 1);
-    if (L.max_fin[2])
-        hipLaunchKernelGGL((k_finish<KB, I2, PAY>), dim3(grid_for(k_finish<KB, I2, PAY>, L.max_fin[2])),
-                           dim3(THREADS), 0, st, w, 2);
-    if (L.max_fin[3])
-        hipLaunchKernelGGL((k_finish<KB, I3, PAY>), dim3(grid_for(k_finish<KB, I3, PAY>, L.max_fin[3])),
-                           dim3(THREADS), 0, st, w, 3);
+    if (L.max_fin[0]) {
+        Timed tm(st, "k_finish0", -1);
+        hipLaunchKernelGGL((k_finish<KB, FIN_BT, I0, PAY>),
+                           dim3(grid_for(k_finish<KB, FIN_BT, I0, PAY>, L.max_fin[0], FIN_BT)), dim3(FIN_BT), 0, st,
+                           w, 0);
+    }
+    if (L.max_fin[1]) {
+        Timed tm(st, "k_finish1", -1);
+        hipLaunchKernelGGL((k_finish<KB, FIN_BT, I1, PAY>),
+                           dim3(grid_for(k_finish<KB, FIN_BT, I1, PAY>, L.max_fin[1], FIN_BT)), dim3(FIN_BT), 0, st,
+                           w, 1);
+    }
+    if (L.max_fin[2]) {
+        Timed tm(st, "k_finish2", -1);
+        hipLaunchKernelGGL((k_finish<KB, FIN_BT, I2, PAY>),
+                           dim3(grid_for(k_finish<KB, FIN_BT, I2, PAY>, L.max_fin[2], FIN_BT)), dim3(FIN_BT), 0, st,
+                           w, 2);
+    }
+    if (L.max_fin[3]) {
+        Timed tm(st, "k_finish3", -1);
+        hipLaunchKernelGGL((k_finish<KB, FIN_BT, I3, PAY>),
+                           dim3(grid_for(k_finish<KB, FIN_BT, I3, PAY>, L.max_fin[3], FIN_BT)), dim3(FIN_BT), 0, st,
+                           w, 3);
+    }
     return hipGetLastError() == hipSuccess ? BINAR_OK : BINAR_EDEVICE;
 }
 
 template <int KB, bool PAY>
 int dispatch_k(const Resolved &r, const Work &w, const Layout &L, const uint32_t *so, uint32_t ns,
                uint32_t n, hipStream_t st) {
-#define BINAR_CASE(KK, TT)                                      \
-    if (r.k == KK && r.tile == THREADS * TT)                    \
-        return enqueue<KB, KK, TT, PAY>(w, L, so, ns, n, st);
-    BINAR_CASE(8, 16)
-    BINAR_CASE(8, 8)
-    BINAR_CASE(4, 16)
-    BINAR_CASE(4, 8)
-    BINAR_CASE(1, 16)
-    BINAR_CASE(1, 8)
+#define BINAR_CASE(KK, TT)                                                  \
+    if (r.k == KK && r.tile == TT)                                          \
+        return r.lookback ? enqueue<KB, KK, TT, PAY, true>(w, L, so, ns, n, st) \
+                          : enqueue<KB, KK, TT, PAY, false>(w, L, so, ns, n, st);
+    if constexpr (KB <= 8) {
+        BINAR_CASE(8, 8192)  // 8192 16-byte keys do not fit in LDS
+    }
+    BINAR_CASE(8, 4096)
+    BINAR_CASE(8, 2048)
+    BINAR_CASE(4, 4096)
+    BINAR_CASE(4, 2048)
+    BINAR_CASE(1, 4096)
+    BINAR_CASE(1, 2048)
 #undef BINAR_CASE
     return BINAR_EINVAL;
 }
@@ -387,9 +514,14 @@ int binar_stats_read(const void *workspace, void *stream, binar_stats *out) {
         out->moved[j] = c.moved[j];
         out->hist_keys[j] = c.hist_keys[j];
     }
-    out->finish_keys = c.fin_keys;
-    out->finish_segments = c.fin_segs;
+    for (int k = 0; k < NCLASS; ++k) {
+        out->finish_class_keys[k] = c.fin_keys[k];
+        out->finish_class_segments[k] = c.fin_segs[k];
+        out->finish_keys += c.fin_keys[k];
+        out->finish_segments += c.fin_segs[k];
+    }
     out->passes = c.passes;
+    out->copyback_keys = c.cpy_keys;
     out->status = (c.error & ERR_SEGMENTS) ? BINAR_EINVAL
                   : ((c.error & ERR_INTERNAL) || c.overflow) ? BINAR_EDEVICE : BINAR_OK;
     return BINAR_OK;
@@ -403,7 +535,7 @@ int binar_get_default_params(uint32_t key_bytes, int has_payload, binar_params *
     out->digit_bits = r.k;
     out->tile_keys = r.tile;
     out->finish_max = r.T;
-    out->reserved = 0;
+    out->offsets = r.lookback ? 2u : 1u;
     return BINAR_OK;
 }
 
@@ -411,9 +543,46 @@ int binar_set_default_params(uint32_t key_bytes, int has_payload, const binar_pa
     if (!valid_kb(key_bytes) || !p) return BINAR_EINVAL;
     if (p->digit_bits && !supported_k(p->digit_bits)) return BINAR_EINVAL;
     if (p->tile_keys && !supported_tile(p->tile_keys)) return BINAR_EINVAL;
+    if (p->offsets > 2) return BINAR_EINVAL;
     std::lock_guard<std::mutex> lk(g_mu);
     g_defaults[kb_index(key_bytes)][has_payload ? 1 : 0] = *p;
     return BINAR_OK;
+}
+
+int binar_profile_enable(int on) {
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.on = on != 0;
+    if (!g_prof.on) {
+        for (auto &r : g_prof.recs) {
+            g_prof.spare.push_back(r.a);
+            g_prof.spare.push_back(r.b);
+        }
+        g_prof.recs.clear();
+    }
+    return BINAR_OK;
+}
+
+int binar_profile_read(binar_launch_time *out, uint32_t cap, uint32_t *count) {
+    if (!count || (!out && cap)) return BINAR_EINVAL;
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    uint32_t k = 0;
+    int rc = BINAR_OK;
+    for (auto &r : g_prof.recs) {
+        if (k < cap) {
+            float ms = 0.f;
+            if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess)
+                rc = BINAR_EDEVICE;
+            std::memcpy(out[k].name, r.name, sizeof(out[k].name));
+            out[k].pass = r.pass;
+            out[k].ms = ms;
+            ++k;
+        }
+        g_prof.spare.push_back(r.a);
+        g_prof.spare.push_back(r.b);
+    }
+    g_prof.recs.clear();
+    *count = k;
+    return rc;
 }
 
 const char *binar_strerror(int status) {

@@ -4,27 +4,39 @@
 // pass takes every live segment larger than the LDS-finish threshold T and
 // partitions it stably on its next k bits (section "Partition Array into
 // Sub-arrays", with the exchange replaced by a stable scatter, k bits at a
-// time instead of one):
+// time instead of one; k stable binary partitions in a row are one stable
+// 2^k-way partition):
 //
-//   k_hist    digit counts of every live segment + AND/OR of its keys
-//   k_plan    per segment: pass-through test (one non-empty digit bin, the
+//   k_hist    digit counts of every live segment, per "piece" (the tiles of
+//             one segment inside one block's chunk), + AND/OR of its keys
+//   k_pscan   per segment and digit: exclusive prefix of the piece counts
+//             over the segment's pieces, and the segment's digit totals
+//   k_plan    per segment: pass-through test (one non-empty digit bin: the
 //             iteration of section "Optimize the Algorithm"), bucket bases
-//             (exclusive scan), classification of the children: done (one
-//             key or no varying bits left: the base cases of section
-//             "Evaluate for Recursive Base Case"), LDS finish, or next pass
-//   k_scatter per tile: stable rank by wave64 ballots, decoupled look-back
-//             prefix across the segment's tiles, LDS staging in digit order,
-//             coalesced write of keys and payload
+//             (exclusive scan over digits), classification of the children:
+//             done (one key or no varying bits left: the base cases of
+//             section "Evaluate for Recursive Base Case"), LDS finish, or the
+//             next pass
+//   k_scatter per tile: stable rank by wave64 ballots, LDS staging in digit
+//             order, coalesced write of keys and payload.  Bucket offsets
+//             come either from the piece prefixes (each block walks its chunk
+//             in order, carrying running offsets: no inter-block waits), or,
+//             in the look-back variant, from a decoupled look-back over the
+//             segment's earlier tiles (Merrill & Garland, 2016).
 //
 // after which k_finish sorts each small segment inside one workgroup (LDS
 // least-significant-digit passes over its remaining varying bits) and
 // writes it to the caller's buffer.
 //
 // Data live in two ping-pong buffer pairs: A (the caller's keys/payload) and
-// B (scratch).  A segment's `parity` says which one holds it; every pass
-// writes the other one, except that finished children are written straight
-// to A.  Segments never overlap, so a finished segment is never touched
-// again by later passes.
+// B (scratch).  A segment's `parity` says which one holds it; a pass always
+// writes the other buffer, because other tiles of the same segment may still
+// be reading the source range.  Children that are finished (one key, or no
+// varying bits left) therefore land in A only when their parent sat in B;
+// finished children of a parent in A land in B and are copied back by
+// k_copyback (runs of adjacent finished children merged into one range).
+// Segments never overlap, so a finished segment is never touched again by
+// later passes.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -37,14 +49,13 @@ namespace binar {
 constexpr int WAVE = 64;
 constexpr int THREADS = 256;
 constexpr int WAVES = THREADS / WAVE;
-constexpr int MAX_RADIX = 256;
 constexpr int NCLASS = 4;        // LDS-finish size classes
-constexpr int MAX_PASSES = 16;   // 128 bits / 8 bits
+constexpr int MAX_PASSES = 16;   // statistics slots (128 bits / 8 bits)
 
 constexpr uint32_t SEG_SKIP = 1u;  // segment does not scatter this pass
 constexpr uint32_t ST_FLAGS = 3u << 30;
-constexpr uint32_t ST_AGG = 1u << 30;  // status word: tile aggregate only
-constexpr uint32_t ST_INC = 2u << 30;  // status word: inclusive prefix
+constexpr uint32_t ST_AGG = 1u << 30;  // look-back word: tile aggregate only
+constexpr uint32_t ST_INC = 2u << 30;  // look-back word: inclusive prefix
 constexpr uint32_t ST_VAL = (1u << 30) - 1u;
 // Bound on every look-back wait (s_sleep rounds).  A predecessor tile always
 // publishes within microseconds; the bound only guarantees that no wave can
@@ -65,34 +76,46 @@ struct FinEntry {
 
 struct Ctl {
     unsigned long long list_ctr[2];  // (entries << 32) | tiles of each pass list
-    unsigned int ticket;             // scatter tile tickets
+    unsigned int ticket;             // look-back scatter: tile tickets
     unsigned int error;              // ERR_SEGMENTS / ERR_INTERNAL
     unsigned int overflow;           // a list ran out of room (never expected)
     unsigned int passes;
     unsigned int fin_ctr[NCLASS];
     unsigned long long moved[MAX_PASSES];
     unsigned long long hist_keys[MAX_PASSES];
-    unsigned long long fin_keys;
-    unsigned long long fin_segs;
+    unsigned long long fin_keys[NCLASS];
+    unsigned long long fin_segs[NCLASS];
+    unsigned int cpy_ctr;            // copy-back ranges
+    unsigned int pad;
+    unsigned long long cpy_keys;
+};
+
+// A range [begin, begin + len) to copy from B to A after the passes.
+struct CopyEntry {
+    uint32_t begin, len;
 };
 
 struct Work {
     Ctl *ctl;
     SegEntry *list[2];
-    uint32_t *counts[2];        // [entry][radix]
-    uint32_t *bases[2];         // [entry][radix]: bucket start
-    uint8_t *to_a[2];           // [entry][radix]: 1 = write this bucket to A
+    uint32_t *counts[2];           // [entry][radix]: digit totals of the segment
+    uint32_t *bases[2];            // [entry][radix]: bucket start (global index)
     unsigned long long *andor[2];  // [entry][4]: and.hi, and.lo, or.hi, or.lo
-    uint32_t *status;           // [tile][radix]
+    uint32_t *pcnt;                // [tile][radix]: piece counts -> piece prefixes (row = piece's first tile)
+    uint32_t *status;              // [tile][radix]: look-back words (look-back variant only)
     FinEntry *fin[NCLASS];
-    uint32_t fin_cap[NCLASS];   // largest segment of each class
-    uint32_t max_fin[NCLASS];   // entries each class can hold
+    CopyEntry *cpy;
+    uint32_t max_cpy;
+    uint32_t fin_cap[NCLASS];      // largest segment of each class
+    uint32_t max_fin[NCLASS];      // entries each class can hold
     uint32_t max_big, max_tiles;
-    uint32_t finish_max;        // T
+    uint32_t finish_max;           // T
     uint32_t tile_keys;
-    uint32_t n_total;           // keys in A and B: every index written is below it
-    void *keys[2];              // A, B
-    uint32_t *pay[2];           // A, B (NULL without payload)
+    uint32_t n_total;              // keys in A and B: every index written is below it
+    uint32_t chunk_grid;           // blocks of k_hist / k_scatter: fixes the pieces
+    uint32_t nbits;                // leading key bits to sort by (the key width unless limited)
+    void *keys[2];                 // A, B
+    uint32_t *pay[2];              // A, B (NULL without payload)
 };
 
 // ------------------------------------------------------------ small helpers
@@ -102,7 +125,17 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-__device__ __forceinline__ uint32_t ld_acquire_agent(const uint32_t *p) {
+// Values every lane of a wave holds alike, made visibly uniform so the
+// compiler keeps them (and addresses built from them) in scalar registers.
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ SegEntry uni(const SegEntry &e) {
+    return SegEntry{uni(e.begin), uni(e.len), uni(e.info), uni(e.tile_start)};
+}
+
+__device__ __forceinline__ FinEntry uni(const FinEntry &e) { return FinEntry{uni(e.begin), uni(e.info)}; }
+
+__device__ __forceinline__ uint32_t ld_agent(const uint32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -110,13 +143,12 @@ __device__ __forceinline__ void st_agent(uint32_t *p, uint32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ unsigned long long ld_u64(const unsigned long long *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Exclusive scan of one value per thread over the block; returns the
-// exclusive prefix and writes the block total to *total.  tmp: WAVES words.
+// Exclusive scan of one value per thread over a block of BT threads;
+// returns the exclusive prefix and writes the block total to *total.
+// tmp: BT / 64 words.
+template <int BT = THREADS>
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *tmp, uint32_t *total) {
+    constexpr int WAVES = BT / WAVE;
     const int lane = lane_id();
     const int wv = threadIdx.x / WAVE;
     uint32_t x = v;
@@ -139,53 +171,54 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *tmp, u
     return before + x - v;
 }
 
-// Stable multisplit rank inside a wave: lanes holding the same digit d are
-// ranked by lane order.  Returns this lane's rank among them and the number
-// of lanes holding d (valid lanes only).
-template <int K>
-__device__ __forceinline__ void wave_match(uint32_t d, bool valid, uint32_t &rank, uint32_t &cnt) {
-    uint64_t m = __ballot(valid);
+// Stable rank of every key of a wave's ITEMS steps (64 consecutive keys per
+// step) among the keys with the same digit: keys of earlier steps of this
+// wave + earlier lanes of this step.
+//   tbl  : this wave's two tables of R 64-bit lane masks in LDS (zero on
+//          entry and exit)
+//   whist: this wave's R counters in LDS (zero on entry; the wave's digit
+//          counts on exit)
+// Steps go in groups of P (1 or 2), step j on table j % P: every lane
+// ORs its lane bit into tbl[digit] and reads the word back -- the mask of
+// the lanes holding its digit -- then clears it.  The highest lane of each
+// mask adds the group size to whist[digit] with an LDS atomic and the others
+// take the old value from it.  A wave's LDS operations execute in issue
+// order, so the counters advance step by step and the ranks follow the input
+// order; P tables let the P steps of a group overlap.  FULL: every
+// key of the tile is valid.
+template <int R, int P, int ITEMS, bool FULL>
+__device__ __forceinline__ void wave_rank(const uint32_t (&dg)[ITEMS], uint32_t ebase, uint32_t len,
+                                          unsigned long long *tbl, uint32_t *whist, uint32_t (&rnk)[ITEMS]) {
+    const unsigned long long me = 1ull << lane_id();
 #pragma unroll
-    for (int b = 0; b < K; ++b) {
-        const bool bit = (d >> b) & 1u;
-        const uint64_t bal = __ballot(bit);
-        m &= bit ? bal : ~bal;
+    for (int j0 = 0; j0 < ITEMS; j0 += P) {
+        bool valid[P];
+        unsigned long long m[P];
+#pragma unroll
+        for (int g = 0; g < P; ++g) {
+            valid[g] = (j0 + g < ITEMS) && (FULL || ebase + (uint32_t)(j0 + g) * WAVE < len);
+            if (valid[g]) atomicOr(&tbl[g * R + dg[j0 + g]], me);
+        }
+#pragma unroll
+        for (int g = 0; g < P; ++g) m[g] = valid[g] ? tbl[g * R + dg[j0 + g]] : 0ull;
+#pragma unroll
+        for (int g = 0; g < P; ++g)
+            if (valid[g]) tbl[g * R + dg[j0 + g]] = 0ull;
+        uint32_t lead[P], got[P];
+#pragma unroll
+        for (int g = 0; g < P; ++g) {
+            if (j0 + g >= ITEMS) break;
+            const uint32_t r = lanes_below(m[g]);
+            const uint32_t c = (uint32_t)__popcll(m[g]);
+            lead[g] = 63u - (uint32_t)__clzll(m[g] | 1ull);
+            rnk[j0 + g] = r;
+            got[g] = 0u;
+            if (valid[g] && r + 1u == c) got[g] = atomicAdd(&whist[dg[j0 + g]], c);
+        }
+#pragma unroll
+        for (int g = 0; g < P; ++g)
+            if (j0 + g < ITEMS) rnk[j0 + g] += (uint32_t)__shfl((int)got[g], (int)lead[g], WAVE);
     }
-    rank = lanes_below(m);
-    cnt = (uint32_t)__popcll(m);
-}
-
-// Append a live segment to pass list L; its counts / AND-OR slot is cleared.
-template <int R>
-__device__ void append_big(const Work &w, int L, uint32_t begin, uint32_t len, uint32_t bitpos,
-                           uint32_t parity) {
-    const uint32_t ntiles = (len + w.tile_keys - 1) / w.tile_keys;
-    const unsigned long long old = atomicAdd(&w.ctl->list_ctr[L], (1ull << 32) | (unsigned long long)ntiles);
-    const uint32_t slot = (uint32_t)(old >> 32);
-    if (slot >= w.max_big || (uint32_t)old + ntiles > w.max_tiles) {
-        atomicOr(&w.ctl->overflow, 1u);
-        return;
-    }
-    w.list[L][slot] = SegEntry{begin, len, bitpos | (parity << 8), (uint32_t)old};
-    uint32_t *c = w.counts[L] + (size_t)slot * R;
-    for (int d = 0; d < R; ++d) c[d] = 0u;
-    unsigned long long *ao = w.andor[L] + (size_t)slot * 4;
-    ao[0] = ~0ull;
-    ao[1] = ~0ull;
-    ao[2] = 0ull;
-    ao[3] = 0ull;
-}
-
-__device__ __forceinline__ void append_fin(const Work &w, uint32_t begin, uint32_t len, uint32_t bitpos,
-                                           uint32_t parity) {
-    int c = 0;
-    while (c < NCLASS - 1 && len > w.fin_cap[c]) ++c;
-    const uint32_t slot = atomicAdd(&w.ctl->fin_ctr[c], 1u);
-    if (slot >= w.max_fin[c]) {
-        atomicOr(&w.ctl->overflow, 1u);
-        return;
-    }
-    w.fin[c][slot] = FinEntry{begin, len | (bitpos << 16) | (parity << 24)};
 }
 
 // ------------------------------------------------------------------ k_reset
@@ -194,28 +227,88 @@ __global__ void k_reset(Ctl *ctl) {
     for (uint32_t i = threadIdx.x; i < sizeof(Ctl) / 4; i += blockDim.x) p[i] = 0u;
 }
 
+// Block-aggregated appends of the children a block found: category q of
+// thread's child: 0..NCLASS-1 = LDS-finish class, NCLASS = next pass list,
+// -1 = none.  Each category reserves one contiguous range with one atomic;
+// next-pass entries reserve their list slots and tiles together, so the list
+// stays ordered by tile_start.
+template <int R>
+__device__ void block_append(const Work &w, int Lnext, int cat, uint32_t begin, uint32_t len, uint32_t bitpos,
+                             uint32_t parity, uint32_t *s_tmp, uint32_t *s_base) {
+    uint32_t idx[NCLASS + 1];
+    uint32_t tot[NCLASS + 1];
+#pragma unroll
+    for (int q = 0; q <= NCLASS; ++q) idx[q] = block_excl_scan(cat == q ? 1u : 0u, s_tmp, &tot[q]);
+    const uint32_t ntiles = (cat == NCLASS) ? (len + w.tile_keys - 1) / w.tile_keys : 0u;
+    uint32_t tot_tiles;
+    const uint32_t tidx = block_excl_scan(ntiles, s_tmp, &tot_tiles);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < NCLASS; ++q) s_base[q] = tot[q] ? atomicAdd(&w.ctl->fin_ctr[q], tot[q]) : 0u;
+        if (tot[NCLASS]) {
+            const unsigned long long old = atomicAdd(&w.ctl->list_ctr[Lnext],
+                                                     ((unsigned long long)tot[NCLASS] << 32) | tot_tiles);
+            s_base[NCLASS] = (uint32_t)(old >> 32);
+            s_base[NCLASS + 1] = (uint32_t)old;
+        }
+    }
+    __syncthreads();
+    if (cat >= 0 && cat < NCLASS) {
+        const uint32_t slot = s_base[cat] + idx[cat];
+        if (slot < w.max_fin[cat])
+            w.fin[cat][slot] = FinEntry{begin, len | (bitpos << 16) | (parity << 24)};
+        else
+            atomicOr(&w.ctl->overflow, 1u);
+    } else if (cat == NCLASS) {
+        const uint32_t slot = s_base[NCLASS] + idx[NCLASS];
+        const uint32_t ts = s_base[NCLASS + 1] + tidx;
+        if (slot < w.max_big && ts + ntiles <= w.max_tiles) {
+            w.list[Lnext][slot] = SegEntry{begin, len, bitpos | (parity << 8), ts};
+            unsigned long long *ao = w.andor[Lnext] + (size_t)slot * 4;
+            ao[0] = ~0ull;
+            ao[1] = ~0ull;
+            ao[2] = 0ull;
+            ao[3] = 0ull;
+        } else {
+            atomicOr(&w.ctl->overflow, 1u);
+        }
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ int fin_class(const Work &w, uint32_t len) {
+    int c = 0;
+    while (c < NCLASS - 1 && len > w.fin_cap[c]) ++c;
+    return c;
+}
+
 // ------------------------------------------------------------------- k_init
 // Classify the caller's segments: <= 1 key: nothing to do (base case);
 // <= T keys: LDS finish; larger: first global pass.
 template <int R>
 __global__ __launch_bounds__(THREADS) void k_init(Work w, const uint32_t *seg_off, uint32_t nseg,
                                                   uint32_t n_single, uint32_t n_limit) {
-    for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < nseg; s += gridDim.x * blockDim.x) {
-        uint32_t b = 0, e = n_single;
-        if (seg_off) {
-            b = seg_off[s];
-            e = seg_off[s + 1];
+    __shared__ uint32_t s_tmp[WAVES];
+    __shared__ uint32_t s_base[NCLASS + 2];
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t s0 = blockIdx.x * blockDim.x; s0 < nseg; s0 += stride) {
+        const uint32_t s = s0 + threadIdx.x;
+        int cat = -1;
+        uint32_t b = 0, len = 0;
+        if (s < nseg) {
+            uint32_t e = n_single;
+            if (seg_off) {
+                b = seg_off[s];
+                e = seg_off[s + 1];
+            }
             if (e < b || e > n_limit) {
                 atomicOr(&w.ctl->error, ERR_SEGMENTS);
-                continue;
+            } else {
+                len = e - b;
+                if (len > 1) cat = (len <= w.finish_max) ? fin_class(w, len) : NCLASS;
             }
         }
-        const uint32_t len = e - b;
-        if (len <= 1) continue;
-        if (len <= w.finish_max)
-            append_fin(w, b, len, 0u, 0u);
-        else
-            append_big<R>(w, 0, b, len, 0u, 0u);
+        block_append<R>(w, 0, cat, b, len, 0u, 0u, s_tmp, s_base);
     }
 }
 
@@ -232,18 +325,49 @@ __device__ __forceinline__ uint32_t find_slot(const SegEntry *list, uint32_t nsl
     return lo;
 }
 
+__device__ __forceinline__ uint32_t seg_tile_end(const SegEntry *list, uint32_t slot, uint32_t nslots,
+                                                 uint32_t ntiles) {
+    return (slot + 1 < nslots) ? list[slot + 1].tile_start : ntiles;
+}
+
+// 16-byte vector of keys: 4 (u32), 2 (u64) or 1 (16-byte string).
+template <int KB>
+struct Vec {
+    static constexpr int N = 16 / KB;
+};
+
+template <int KB>
+__device__ __forceinline__ void load_vec(const void *p, size_t i, typename KeyT<KB>::V (&v)[Vec<KB>::N]) {
+    if constexpr (KB == 4) {
+        const uint4 x = *reinterpret_cast<const uint4 *>(reinterpret_cast<const uint32_t *>(p) + i);
+        v[0] = x.x;
+        v[1] = x.y;
+        v[2] = x.z;
+        v[3] = x.w;
+    } else if constexpr (KB == 8) {
+        const ulonglong2 x = *reinterpret_cast<const ulonglong2 *>(reinterpret_cast<const uint64_t *>(p) + i);
+        v[0] = x.x;
+        v[1] = x.y;
+    } else {
+        v[0] = KeyT<16>::load(p, i);
+    }
+}
+
 // ------------------------------------------------------------------- k_hist
 // Digit counts (bits [bitpos, bitpos + w) of each key) and AND/OR of every
-// live segment of list L.  Each block takes a contiguous run of tiles and
-// flushes its LDS counts whenever the segment changes.  Also clears the
-// look-back status words of its tiles and resets the next list and the
-// scatter ticket (nothing else touches them during this kernel).
-template <int KB, int K>
+// live segment of list L.  The tiles of the list are cut into gridDim.x
+// contiguous chunks, one per block; the tiles of one segment inside one
+// chunk form a piece, whose counts go to row pcnt[first tile of the piece].
+// Also resets the next list and the scatter ticket (nothing else touches
+// them during this kernel) and, for the look-back scatter, clears the
+// look-back words of every tile.
+template <int KB, int K, bool LOOKBACK>
 __global__ __launch_bounds__(THREADS) void k_hist(Work w, int L) {
     using KT = KeyT<KB>;
     using V = typename KT::V;
     constexpr int R = 1 << K;
-    constexpr int U = 4;  // keys in flight per thread
+    constexpr int VN = Vec<KB>::N;
+    constexpr int U = 4;  // vectors in flight per thread
     __shared__ uint32_t s_h[WAVES][R];
     __shared__ unsigned long long s_ao[WAVES][4];
 
@@ -263,25 +387,58 @@ __global__ __launch_bounds__(THREADS) void k_hist(Work w, int L) {
 
     const int wv = threadIdx.x / WAVE, lane = lane_id();
     for (int i = threadIdx.x; i < WAVES * R; i += THREADS) (&s_h[0][0])[i] = 0u;
+    if (LOOKBACK)
+        for (size_t i = (size_t)t0 * R + threadIdx.x; i < (size_t)t1 * R; i += THREADS) w.status[i] = 0u;
     __syncthreads();
 
     uint32_t slot = find_slot(w.list[L], nslots, t0);
-    SegEntry seg = w.list[L][slot];
-    uint32_t next_start = (slot + 1 < nslots) ? w.list[L][slot + 1].tile_start : 0xFFFFFFFFu;
-    V a = KT::ones(), o = KT::zero();
-
-    auto flush = [&](uint32_t fslot) {
-        __syncthreads();
-        uint32_t *cnt = w.counts[L] + (size_t)fslot * R;
-        for (int d = threadIdx.x; d < R; d += THREADS) {
-            uint32_t c = 0;
-#pragma unroll
-            for (int q = 0; q < WAVES; ++q) {
-                c += s_h[q][d];
-                s_h[q][d] = 0u;
-            }
-            if (c) atomicAdd(&cnt[d], c);
+    for (uint32_t t = t0; t < t1;) {
+        const SegEntry seg = uni(w.list[L][slot]);
+        const uint32_t te = min(t1, seg_tile_end(w.list[L], slot, nslots, ntiles));
+        const uint32_t bitpos = seg.info & 0xFFu, parity = (seg.info >> 8) & 1u;
+        const int wbits = min(K, (int)w.nbits - (int)bitpos);
+        const void *src = w.keys[parity];
+        const size_t g0 = (size_t)seg.begin + (size_t)(t - seg.tile_start) * w.tile_keys;
+        const size_t g1 = (size_t)seg.begin + min((size_t)seg.len, (size_t)(te - seg.tile_start) * w.tile_keys);
+        V a = KT::ones(), o = KT::zero();
+        // head and tail one key at a time, the 16-byte aligned body 16 bytes at
+        // a time (keys are at least key-size aligned, so `mis` is whole keys)
+        const size_t mis = ((16u - (reinterpret_cast<uintptr_t>(src) & 15u)) & 15u) / KB;
+        const size_t b0 = min(g1, g0 + ((mis + VN - (g0 % VN)) % VN));
+        const size_t b1 = b0 + (g1 - b0) / VN * VN;
+        for (size_t i = g0 + threadIdx.x; i < b0; i += THREADS) {
+            const V v = KT::load(src, i);
+            atomicAdd(&s_h[wv][KT::digit(v, bitpos, wbits)], 1u);
+            a = KT::vand(a, v);
+            o = KT::vor(o, v);
         }
+        for (size_t i = b1 + threadIdx.x; i < g1; i += THREADS) {
+            const V v = KT::load(src, i);
+            atomicAdd(&s_h[wv][KT::digit(v, bitpos, wbits)], 1u);
+            a = KT::vand(a, v);
+            o = KT::vor(o, v);
+        }
+        for (size_t i = b0 + (size_t)threadIdx.x * VN; i < b1; i += (size_t)THREADS * VN * U) {
+            V v[U][VN];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const size_t x = i + (size_t)u * THREADS * VN;
+                if (x < b1) load_vec<KB>(src, x, v[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const size_t x = i + (size_t)u * THREADS * VN;
+                if (x < b1) {
+#pragma unroll
+                    for (int q = 0; q < VN; ++q) {
+                        atomicAdd(&s_h[wv][KT::digit(v[u][q], bitpos, wbits)], 1u);
+                        a = KT::vand(a, v[u][q]);
+                        o = KT::vor(o, v[u][q]);
+                    }
+                }
+            }
+        }
+        // flush the piece: counts to its row, AND/OR to the segment
         Canon ca = KT::canon(a), co = KT::canon(o);
 #pragma unroll
         for (int off = 1; off < WAVE; off <<= 1) {
@@ -297,70 +454,115 @@ __global__ __launch_bounds__(THREADS) void k_hist(Work w, int L) {
             s_ao[wv][3] = co.lo;
         }
         __syncthreads();
+        uint32_t *row = w.pcnt + (size_t)t * R;
+        for (int d = threadIdx.x; d < R; d += THREADS) {
+            uint32_t c = 0;
+#pragma unroll
+            for (int q = 0; q < WAVES; ++q) {
+                c += s_h[q][d];
+                s_h[q][d] = 0u;
+            }
+            row[d] = c;
+        }
         if (threadIdx.x < 4) {
             unsigned long long v = s_ao[0][threadIdx.x];
-            for (int q = 1; q < WAVES; ++q) v = (threadIdx.x < 2) ? (v & s_ao[q][threadIdx.x]) : (v | s_ao[q][threadIdx.x]);
-            unsigned long long *dst = w.andor[L] + (size_t)fslot * 4 + threadIdx.x;
+            for (int q = 1; q < WAVES; ++q)
+                v = (threadIdx.x < 2) ? (v & s_ao[q][threadIdx.x]) : (v | s_ao[q][threadIdx.x]);
+            unsigned long long *dst = w.andor[L] + (size_t)slot * 4 + threadIdx.x;
             if (threadIdx.x < 2)
                 atomicAnd(dst, v);
             else
                 atomicOr(dst, v);
         }
-        a = KT::ones();
-        o = KT::zero();
         __syncthreads();
-    };
+        t = te;
+        ++slot;
+    }
+}
 
-    for (uint32_t t = t0; t < t1; ++t) {
-        if (t >= next_start) {
-            flush(slot);
-            while (slot + 1 < nslots && w.list[L][slot + 1].tile_start <= t) ++slot;
-            seg = w.list[L][slot];
-            next_start = (slot + 1 < nslots) ? w.list[L][slot + 1].tile_start : 0xFFFFFFFFu;
+// ------------------------------------------------------------------ k_pscan
+// For every live segment and digit: the exclusive prefix of its piece counts
+// over the segment's pieces (in tile order, written back in place) and the
+// segment's digit total.  One block per (segment, group of up to 32
+// digits); THREADS / group lanes split the pieces into contiguous runs.
+template <int K>
+__global__ __launch_bounds__(THREADS) void k_pscan(Work w, int L) {
+    constexpr int R = 1 << K;
+    constexpr int DG = R < 32 ? R : 32;          // digits per block
+    constexpr int NG = R / DG;                   // digit groups per segment
+    constexpr int Q = THREADS / DG;              // lanes per digit
+    constexpr int B = 8;                         // loads in flight per lane
+    __shared__ uint32_t s_part[Q][DG];
+
+    Ctl *ctl = w.ctl;
+    if (ctl->error | ctl->overflow) return;
+    const unsigned long long lc = ctl->list_ctr[L];
+    const uint32_t nslots = (uint32_t)(lc >> 32), ntiles = (uint32_t)lc;
+    if (nslots == 0) return;
+    const uint32_t per = (ntiles + w.chunk_grid - 1) / w.chunk_grid;
+    const int dl = threadIdx.x % DG, q = threadIdx.x / DG;
+
+    for (uint32_t item = blockIdx.x; item < nslots * NG; item += gridDim.x) {
+        const uint32_t slot = item / NG;
+        const int d = (int)(item % NG) * DG + dl;
+        const SegEntry seg = w.list[L][slot];
+        const uint32_t ts = seg.tile_start;
+        const uint32_t te = seg_tile_end(w.list[L], slot, nslots, ntiles);
+        // pieces: ts, then every chunk start inside (ts, te)
+        const uint32_t c0 = ts / per;
+        const uint32_t np = (te - 1) / per - c0 + 1;
+        const uint32_t p0 = (uint32_t)(((unsigned long long)np * q) / Q);
+        const uint32_t p1 = (uint32_t)(((unsigned long long)np * (q + 1)) / Q);
+        auto row = [&](uint32_t p) -> uint32_t * {
+            const uint32_t t = (p == 0) ? ts : (c0 + p) * per;
+            return w.pcnt + (size_t)t * R + d;
+        };
+        uint32_t part = 0;
+        for (uint32_t p = p0; p < p1; p += B) {
+            uint32_t v[B];
+#pragma unroll
+            for (int i = 0; i < B; ++i) v[i] = (p + i < p1) ? *row(p + i) : 0u;
+#pragma unroll
+            for (int i = 0; i < B; ++i) part += v[i];
         }
-        // clear this tile's look-back status words
-        for (int d = threadIdx.x; d < R; d += THREADS) w.status[(size_t)t * R + d] = 0u;
-
-        const uint32_t bitpos = seg.info & 0xFFu, parity = (seg.info >> 8) & 1u;
-        const int wbits = min(K, KT::NBITS - (int)bitpos);
-        const void *src = w.keys[parity];
-        const uint32_t lt = t - seg.tile_start;
-        const uint32_t e0 = lt * w.tile_keys;
-        const uint32_t e1 = min(seg.len, e0 + w.tile_keys);
-        for (uint32_t e = e0 + threadIdx.x; e < e1; e += THREADS * U) {
-            V v[U];
+        s_part[q][dl] = part;
+        __syncthreads();
+        uint32_t run = 0, total = 0;
+        for (int k = 0; k < Q; ++k) {
+            const uint32_t x = s_part[k][dl];
+            if (k < q) run += x;
+            total += x;
+        }
+        __syncthreads();
+        if (q == 0) w.counts[L][(size_t)slot * R + d] = total;
+        for (uint32_t p = p0; p < p1; p += B) {
+            uint32_t v[B];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const uint32_t x = e + u * THREADS;
-                v[u] = (x < e1) ? KT::load(src, (size_t)seg.begin + x) : KT::zero();
-            }
+            for (int i = 0; i < B; ++i) v[i] = (p + i < p1) ? *row(p + i) : 0u;
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const uint32_t x = e + u * THREADS;
-                if (x < e1) {
-                    atomicAdd(&s_h[wv][KT::digit(v[u], bitpos, wbits)], 1u);
-                    a = KT::vand(a, v[u]);
-                    o = KT::vor(o, v[u]);
-                }
+            for (int i = 0; i < B; ++i) {
+                if (p + i < p1) *row(p + i) = run;
+                run += v[i];
             }
         }
     }
-    flush(slot);
 }
 
 // ------------------------------------------------------------------- k_plan
 template <int KB, int K>
 __global__ __launch_bounds__(THREADS) void k_plan(Work w, int L, int pass) {
-    using KT = KeyT<KB>;
     constexpr int R = 1 << K;
-    constexpr int NB = KT::NBITS;
+    const int NB = (int)w.nbits;
     __shared__ uint32_t s_tmp[WAVES];
+    __shared__ uint32_t s_base[NCLASS + 3];
+    __shared__ uint32_t s_state[THREADS];
     Ctl *ctl = w.ctl;
     if (ctl->error | ctl->overflow) return;
     const unsigned long long lc = ctl->list_ctr[L];
     const uint32_t nslots = (uint32_t)(lc >> 32);
     if (nslots == 0) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicMax(&ctl->passes, (unsigned)(pass + 1));
+    const int ps = pass < MAX_PASSES ? pass : MAX_PASSES - 1;
     const int d = threadIdx.x;
 
     for (uint32_t s = blockIdx.x; s < nslots; s += gridDim.x) {
@@ -372,142 +574,203 @@ __global__ __launch_bounds__(THREADS) void k_plan(Work w, int L, int pass) {
         const int nz = __syncthreads_count(c != 0u);
         const unsigned long long *ao = w.andor[L] + (size_t)s * 4;
         const Canon diff{ao[0] ^ ao[2], ao[1] ^ ao[3]};
-        const int ps = pass < MAX_PASSES ? pass : MAX_PASSES - 1;
         if (d == 0) atomicAdd(&ctl->hist_keys[ps], (unsigned long long)seg.len);
 
         if (nz == 1) {
             // pass-through: every key has the same digit here
             const int nb = first_set_from(diff, bitpos, NB);
+            int cat = -1;
             if (nb >= NB) {
                 // all keys equal: done; if they sit in B the scatter copies them to A
                 if (parity == 1u) {
-                    if (c != 0u) {
-                        w.bases[L][(size_t)s * R + d] = seg.begin;
-                        w.to_a[L][(size_t)s * R + d] = 1;
-                    }
+                    if (c != 0u) w.bases[L][(size_t)s * R + d] = seg.begin;
                     if (d == 0) atomicAdd(&ctl->moved[ps], (unsigned long long)seg.len);
                 } else if (d == 0) {
                     w.list[L][s].info = seg.info | (SEG_SKIP << 16);
                 }
-            } else if (d == 0) {
-                w.list[L][s].info = seg.info | (SEG_SKIP << 16);
-                append_big<R>(w, L ^ 1, seg.begin, seg.len, (uint32_t)nb, parity);
+            } else {
+                if (d == 0) {
+                    w.list[L][s].info = seg.info | (SEG_SKIP << 16);
+                    cat = NCLASS;
+                }
             }
-            __syncthreads();
+            block_append<R>(w, L ^ 1, cat, seg.begin, seg.len, nb < NB ? (uint32_t)nb : 0u, parity, s_tmp,
+                            s_base);
             continue;
         }
 
         uint32_t total;
         const uint32_t excl = block_excl_scan(c, s_tmp, &total);
+        int cat = -1;
+        uint32_t cb = 0;
+        bool done = false;
+        const uint32_t child_parity = parity ^ 1u;
         if (c != 0u) {
-            const uint32_t cb = (uint32_t)first_set_from(diff, bitpos + wbits, NB);
-            const uint32_t child_parity = parity ^ 1u;
-            const bool done = (c == 1u) || (cb >= (uint32_t)NB);
+            cb = (uint32_t)first_set_from(diff, bitpos + wbits, NB);
+            done = (c == 1u) || (cb >= (uint32_t)NB);
             w.bases[L][(size_t)s * R + d] = seg.begin + excl;
-            w.to_a[L][(size_t)s * R + d] = (done || child_parity == 0u) ? 1 : 0;
-            if (!done) {
-                if (c <= w.finish_max)
-                    append_fin(w, seg.begin + excl, c, cb, child_parity);
-                else
-                    append_big<R>(w, L ^ 1, seg.begin + excl, c, cb, child_parity);
-            }
+            if (!done) cat = (c <= w.finish_max) ? fin_class(w, c) : NCLASS;
         }
         if (d == 0) atomicAdd(&ctl->moved[ps], (unsigned long long)seg.len);
-        __syncthreads();
+        if (parity == 0u) {
+            // finished children land in B: one copy-back range per run of
+            // adjacent finished children (empty digits do not break a run)
+            s_state[d] = (c == 0u) ? 0u : (done ? 1u : 2u);
+            __syncthreads();
+            bool head = false;
+            uint32_t run = 0;
+            if (d < R && s_state[d] == 1u) {
+                int e = d - 1;
+                while (e >= 0 && s_state[e] == 0u) --e;
+                head = (e < 0) || (s_state[e] == 2u);
+                if (head) {
+                    for (int f = d; f < R && s_state[f] != 2u; ++f) run += w.counts[L][(size_t)s * R + f];
+                }
+            }
+            uint32_t nh;
+            const uint32_t hi = block_excl_scan(head ? 1u : 0u, s_tmp, &nh);
+            if (d == 0 && nh) s_base[NCLASS + 2] = atomicAdd(&ctl->cpy_ctr, nh);
+            __syncthreads();
+            if (head) {
+                const uint32_t slot = s_base[NCLASS + 2] + hi;
+                if (slot < w.max_cpy)
+                    w.cpy[slot] = CopyEntry{seg.begin + excl, run};
+                else
+                    atomicOr(&ctl->overflow, 1u);
+            }
+        }
+        block_append<R>(w, L ^ 1, cat, seg.begin + excl, c, cb, child_parity, s_tmp, s_base);
+    }
+}
+
+// -------------------------------------------------------------- k_copyback
+// Copy the finished ranges that the passes left in B to A.
+template <int KB, bool PAY>
+__global__ __launch_bounds__(THREADS) void k_copyback(Work w) {
+    using KT = KeyT<KB>;
+    Ctl *ctl = w.ctl;
+    if (ctl->error | ctl->overflow) return;
+    const uint32_t n = min(ctl->cpy_ctr, w.max_cpy);
+    for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
+        const CopyEntry e = w.cpy[i];
+        if ((size_t)e.begin + e.len > w.n_total) {
+            if (threadIdx.x == 0) atomicOr(&ctl->error, ERR_INTERNAL);
+            continue;
+        }
+        if (threadIdx.x == 0) atomicAdd(&ctl->cpy_keys, (unsigned long long)e.len);
+        for (uint32_t k = threadIdx.x; k < e.len; k += THREADS) {
+            const size_t g = (size_t)e.begin + k;
+            KT::store(w.keys[0], g, KT::load(w.keys[1], g));
+            if (PAY) w.pay[0][g] = w.pay[1][g];
+        }
     }
 }
 
 // ---------------------------------------------------------------- k_scatter
-// One tile = THREADS * ITEMS keys of one segment.  Wave q owns keys
+// One tile = BT * ITEMS keys of one segment.  Wave q owns keys
 // [q * ITEMS * 64, (q + 1) * ITEMS * 64) of the tile, 64 consecutive keys per
 // step, so the (wave, step, lane) order is the input order and a stable rank
-// is: keys of the digit in earlier waves + earlier steps of this wave +
-// earlier lanes of this step.
-template <int KB, int K, int ITEMS, bool PAY>
-__global__ __launch_bounds__(THREADS) void k_scatter(Work w, int L) {
+// is: keys of the digit in earlier waves + the rank inside the wave.
+//
+// Bucket offsets of a tile (s_gofs[d] = global index of staged position 0
+// of digit d):
+//   LOOKBACK = false: the block owns the same chunk of tiles as in k_hist and
+//     walks it in order, starting each piece from bases + piece prefix and
+//     advancing by each tile's counts;
+//   LOOKBACK = true: tiles are taken in ticket order and each looks back over
+//     the earlier tiles of its segment (decoupled look-back).
+template <int KB, int K, int BT, int ITEMS, bool PAY>
+struct ScatterLds {
+    using V = typename KeyT<KB>::V;
+    static constexpr int R = 1 << K;
+    static constexpr int TILE = BT * ITEMS;
+    static constexpr int NW = BT / WAVE;
+    static constexpr int P = NW >= 16 ? 1 : 2;  // lane-mask tables per wave (LDS budget)
+    V keys[TILE];
+    uint32_t pay[PAY ? TILE : 1];
+    unsigned long long tbl[NW][P][R];  // lane masks of the wave ranking
+    uint32_t wh[NW][R];             // per-wave digit counts -> staged offset of (wave, digit)
+    uint32_t gofs[R];               // global index of staged position 0 of digit d
+    uint32_t run[R];                // chunked offsets: next global index of digit d in this piece
+    uint32_t tmp[NW];
+    uint32_t tile, slot;
+};
+
+// Keys (and payloads) of tile t of `seg` into registers, wave-striped.
+template <int KB, int BT, int ITEMS, bool PAY>
+__device__ __forceinline__ void load_tile(const Work &w, const SegEntry &seg, uint32_t t,
+                                          typename KeyT<KB>::V (&key)[ITEMS], uint32_t (&pay)[ITEMS]) {
+    using KT = KeyT<KB>;
+    constexpr uint32_t TILE = BT * ITEMS;
+    const uint32_t parity = (seg.info >> 8) & 1u;
+    const uint32_t off = (t - seg.tile_start) * TILE;
+    const uint32_t tlen = min(TILE, seg.len - off);
+    const size_t gbase = (size_t)seg.begin + off;
+    // tile base pointers are uniform: loads use a scalar base + lane offset
+    const char *tsrc = static_cast<const char *>(w.keys[parity]) + gbase * KB;
+    const uint32_t *tpsrc = PAY ? w.pay[parity] + gbase : nullptr;
+    const uint32_t ebase = (uint32_t)(threadIdx.x / WAVE) * ITEMS * WAVE + (uint32_t)lane_id();
+    if (tlen == TILE) {
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            key[j] = KT::load(tsrc, ebase + j * WAVE);
+            if (PAY) pay[j] = tpsrc[ebase + j * WAVE];
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const uint32_t e = ebase + j * WAVE;
+            key[j] = (e < tlen) ? KT::load(tsrc, e) : KT::zero();
+            if (PAY) pay[j] = (e < tlen) ? tpsrc[e] : 0u;
+        }
+    }
+}
+
+// Rank, offsets, stage and write one tile whose keys are in registers.
+template <int KB, int K, int BT, int ITEMS, bool PAY, bool LOOKBACK, bool FULL>
+__device__ __forceinline__ void scatter_tile(const Work &w, int L, ScatterLds<KB, K, BT, ITEMS, PAY> &S,
+                                             const SegEntry &seg, uint32_t t, uint32_t slot,
+                                             const typename KeyT<KB>::V (&key)[ITEMS], const uint32_t (&pay)[ITEMS]) {
     using KT = KeyT<KB>;
     using V = typename KT::V;
     constexpr int R = 1 << K;
-    constexpr int TILE = THREADS * ITEMS;
-    __shared__ V s_keys[TILE];
-    __shared__ uint32_t s_pay[PAY ? TILE : 1];
-    __shared__ uint32_t s_wh[WAVES][R];   // per-wave digit counts -> wave offsets
-    __shared__ uint32_t s_dstart[R];      // digit start inside the staged tile
-    __shared__ uint32_t s_gofs[R];        // global index of staged position 0 of digit d
-    __shared__ uint8_t s_toa[R];
-    __shared__ uint32_t s_tmp[WAVES];
-    __shared__ uint32_t s_tile, s_slot;
-
+    constexpr int TILE = BT * ITEMS;
+    constexpr int NW = BT / WAVE;
     Ctl *ctl = w.ctl;
-    if (ctl->error | ctl->overflow) return;
-    const unsigned long long lc = ctl->list_ctr[L];
-    const uint32_t nslots = (uint32_t)(lc >> 32), ntiles = (uint32_t)lc;
-    if (ntiles == 0) return;
     const int wv = threadIdx.x / WAVE, lane = lane_id();
+    const uint32_t bitpos = seg.info & 0xFFu, parity = (seg.info >> 8) & 1u;
+    const int wbits = min(K, (int)w.nbits - (int)bitpos);
+    const uint32_t lt = t - seg.tile_start;
+    const uint32_t off = lt * (uint32_t)TILE;
+    const uint32_t tlen = FULL ? (uint32_t)TILE : min((uint32_t)TILE, seg.len - off);
+    void *dst = w.keys[parity ^ 1u];
+    uint32_t *pdst = w.pay[parity ^ 1u];
 
-    for (;;) {
-        if (threadIdx.x == 0) {
-            const uint32_t t = atomicAdd(&ctl->ticket, 1u);
-            s_tile = t;
-            s_slot = (t < ntiles) ? find_slot(w.list[L], nslots, t) : 0u;
-        }
-        for (int i = threadIdx.x; i < WAVES * R; i += THREADS) (&s_wh[0][0])[i] = 0u;
-        __syncthreads();
-        const uint32_t t = s_tile;
-        if (t >= ntiles) break;
-        const uint32_t slot = s_slot;
-        const SegEntry seg = w.list[L][slot];
-        if ((seg.info >> 16) & SEG_SKIP) {
-            __syncthreads();
-            continue;
-        }
-        const uint32_t bitpos = seg.info & 0xFFu, parity = (seg.info >> 8) & 1u;
-        const int wbits = min(K, KT::NBITS - (int)bitpos);
-        const uint32_t lt = t - seg.tile_start;
-        const uint32_t off = lt * (uint32_t)TILE;
-        const uint32_t tlen = min((uint32_t)TILE, seg.len - off);
-        const void *src = w.keys[parity];
-        const uint32_t *psrc = w.pay[parity];
-        const size_t gbase = (size_t)seg.begin + off;
-
-        V key[ITEMS];
-        uint32_t pay[ITEMS];
-        uint32_t rnk[ITEMS];
-        const uint32_t ebase = (uint32_t)wv * ITEMS * WAVE + (uint32_t)lane;
+    uint32_t dg[ITEMS];
+    uint32_t rnk[ITEMS];
+    const uint32_t ebase = (uint32_t)wv * ITEMS * WAVE + (uint32_t)lane;
 #pragma unroll
-        for (int j = 0; j < ITEMS; ++j) {
-            const uint32_t e = ebase + j * WAVE;
-            key[j] = (e < tlen) ? KT::load(src, gbase + e) : KT::zero();
-            if (PAY) pay[j] = (e < tlen) ? psrc[gbase + e] : 0u;
-        }
-        // stable rank inside the wave, step by step
+    for (int j = 0; j < ITEMS; ++j) dg[j] = KT::digit(key[j], bitpos, wbits);
+    wave_rank<R, ScatterLds<KB, K, BT, ITEMS, PAY>::P, ITEMS, FULL>(dg, ebase, tlen, &S.tbl[wv][0][0], &S.wh[wv][0],
+                                                                     rnk);
+    __syncthreads();
+    // per digit: staged offset of each wave's keys, tile count, global offset
+    uint32_t tcnt = 0;
+    if (threadIdx.x < R) {
 #pragma unroll
-        for (int j = 0; j < ITEMS; ++j) {
-            const uint32_t e = ebase + j * WAVE;
-            const bool valid = e < tlen;
-            const uint32_t dg = valid ? KT::digit(key[j], bitpos, wbits) : 0u;
-            uint32_t r, c;
-            wave_match<K>(dg, valid, r, c);
-            uint32_t before = 0;
-            if (valid) before = s_wh[wv][dg];
-            rnk[j] = before + r;
-            if (valid && r + 1 == c) s_wh[wv][dg] = before + c;
-        }
-        __syncthreads();
-        // per digit: wave offsets and tile count
-        uint32_t tcnt = 0;
-        if (threadIdx.x < R) {
+        for (int q = 0; q < NW; ++q) tcnt += S.wh[q][threadIdx.x];
+    }
+    uint32_t tot;
+    const uint32_t dstart = block_excl_scan<BT>(tcnt, S.tmp, &tot);  // every thread: it holds barriers
+    if (threadIdx.x < R) {
+        uint32_t acc = dstart;
 #pragma unroll
-            for (int q = 0; q < WAVES; ++q) {
-                const uint32_t x = s_wh[q][threadIdx.x];
-                s_wh[q][threadIdx.x] = tcnt;
-                tcnt += x;
-            }
+        for (int q = 0; q < NW; ++q) {
+            const uint32_t x = S.wh[q][threadIdx.x];
+            S.wh[q][threadIdx.x] = acc;
+            acc += x;
         }
-        uint32_t tot;
-        const uint32_t dstart = block_excl_scan(tcnt, s_tmp, &tot);
-        // decoupled look-back over the earlier tiles of this segment
-        if (threadIdx.x < R) {
+        if (LOOKBACK) {
             uint32_t *st = w.status + (size_t)t * R + threadIdx.x;
             uint32_t excl = 0;
             if (lt == 0) {
@@ -518,7 +781,7 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int L) {
                 uint32_t spins = 0;
                 for (;;) {
                     uint32_t v;
-                    while (((v = ld_acquire_agent(w.status + (size_t)tt * R + threadIdx.x)) & ST_FLAGS) == 0u &&
+                    while (((v = ld_agent(w.status + (size_t)tt * R + threadIdx.x)) & ST_FLAGS) == 0u &&
                            spins < SPIN_LIMIT) {
                         __builtin_amdgcn_s_sleep(1);
                         ++spins;
@@ -534,102 +797,204 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Work w, int L) {
                 }
                 st_agent(st, ST_INC | (excl + tcnt));
             }
-            const size_t bi = (size_t)slot * R + threadIdx.x;
-            s_dstart[threadIdx.x] = dstart;
-            if (tcnt) {
-                s_gofs[threadIdx.x] = w.bases[L][bi] + excl - dstart;
-                s_toa[threadIdx.x] = w.to_a[L][bi];
-            }
+            if (tcnt) S.gofs[threadIdx.x] = w.bases[L][(size_t)slot * R + threadIdx.x] + excl - dstart;
+        } else {
+            S.gofs[threadIdx.x] = S.run[threadIdx.x] - dstart;
+            S.run[threadIdx.x] += tcnt;
         }
-        __syncthreads();
-        // stage in digit order
+    }
+    __syncthreads();
+    // stage in digit order; the wave ranking left its counters at zero
 #pragma unroll
-        for (int j = 0; j < ITEMS; ++j) {
-            const uint32_t e = ebase + j * WAVE;
-            if (e < tlen) {
-                const uint32_t dg = KT::digit(key[j], bitpos, wbits);
-                const uint32_t pos = s_dstart[dg] + s_wh[wv][dg] + rnk[j];
-                s_keys[pos] = key[j];
-                if (PAY) s_pay[pos] = pay[j];
+    for (int j = 0; j < ITEMS; ++j) {
+        const uint32_t e = ebase + j * WAVE;
+        if (FULL || e < tlen) {
+            const uint32_t pos = S.wh[wv][dg[j]] + rnk[j];
+            S.keys[pos] = key[j];
+            if (PAY) S.pay[pos] = pay[j];
+        }
+    }
+    __syncthreads();
+    // coalesced write: consecutive staged keys of one digit go to consecutive
+    // global positions; each wave clears its own counters for the next tile
+    for (int i = lane; i < R; i += WAVE) S.wh[wv][i] = 0u;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const uint32_t p = j * BT + threadIdx.x;
+        if (FULL || p < tlen) {
+            const V k = S.keys[p];
+            const uint32_t g = S.gofs[KT::digit(k, bitpos, wbits)] + p;
+            if (g < w.n_total) {
+                KT::store(dst, g, k);
+                if (PAY) pdst[g] = S.pay[p];
+            } else {
+                atomicOr(&ctl->error, ERR_INTERNAL);
             }
         }
-        __syncthreads();
-        // coalesced write: consecutive staged keys of one digit go to
-        // consecutive global positions
-#pragma unroll 4
-        for (int j = 0; j < ITEMS; ++j) {
-            const uint32_t p = j * THREADS + threadIdx.x;
-            if (p < tlen) {
-                const V k = s_keys[p];
-                const uint32_t dg = KT::digit(k, bitpos, wbits);
-                const uint32_t a = s_toa[dg];
-                const uint32_t g = s_gofs[dg] + p;
-                if (g < w.n_total) {
-                    KT::store(w.keys[a ? 0 : 1], g, k);
-                    if (PAY) w.pay[a ? 0 : 1][g] = s_pay[p];
-                } else {
-                    atomicOr(&ctl->error, ERR_INTERNAL);
-                }
+    }
+    __syncthreads();
+}
+
+template <int KB, int K, int BT, int ITEMS, bool PAY, bool LOOKBACK>
+__global__ __launch_bounds__(BT) void k_scatter(Work w, int L) {
+    using V = typename KeyT<KB>::V;
+    constexpr int R = 1 << K;
+    constexpr uint32_t TILE = BT * ITEMS;
+    constexpr int NW = BT / WAVE;
+    __shared__ ScatterLds<KB, K, BT, ITEMS, PAY> S;
+
+    Ctl *ctl = w.ctl;
+    if (ctl->error | ctl->overflow) return;
+    const unsigned long long lc = ctl->list_ctr[L];
+    const uint32_t nslots = (uint32_t)(lc >> 32), ntiles = (uint32_t)lc;
+    if (ntiles == 0) return;
+    uint32_t t0 = 0, t1 = 0;
+    if (!LOOKBACK) {
+        const uint32_t per = (ntiles + gridDim.x - 1) / gridDim.x;
+        t0 = blockIdx.x * per;
+        t1 = min(ntiles, t0 + per);
+        if (t0 >= t1) return;
+    }
+    for (int i = threadIdx.x; i < NW * R; i += BT) (&S.wh[0][0])[i] = 0u;
+    for (int i = threadIdx.x; i < NW * ScatterLds<KB, K, BT, ITEMS, PAY>::P * R; i += BT) (&S.tbl[0][0][0])[i] = 0ull;
+    __syncthreads();
+
+    V key[ITEMS];
+    uint32_t pay[ITEMS];
+    if (LOOKBACK) {
+        // tiles in ticket order; each looks back over its segment's earlier tiles
+        for (;;) {
+            if (threadIdx.x == 0) {
+                const uint32_t tk = atomicAdd(&ctl->ticket, 1u);
+                S.tile = tk;
+                S.slot = (tk < ntiles) ? find_slot(w.list[L], nslots, tk) : 0u;
             }
+            __syncthreads();
+            const uint32_t t = uni(S.tile);
+            if (t >= ntiles) break;
+            const uint32_t slot = uni(S.slot);
+            const SegEntry seg = uni(w.list[L][slot]);
+            __syncthreads();
+            if ((seg.info >> 16) & SEG_SKIP) continue;
+            load_tile<KB, BT, ITEMS, PAY>(w, seg, t, key, pay);
+            if (seg.len - (t - seg.tile_start) * TILE >= TILE)
+                scatter_tile<KB, K, BT, ITEMS, PAY, true, true>(w, L, S, seg, t, slot, key, pay);
+            else
+                scatter_tile<KB, K, BT, ITEMS, PAY, true, false>(w, L, S, seg, t, slot, key, pay);
         }
-        __syncthreads();
+        return;
+    }
+
+    // chunked: walk tiles t0 .. t1 in order; the next tile of the same segment
+    // is loaded into a second register set while the current one is processed
+    V keyn[ITEMS];
+    uint32_t payn[ITEMS];
+    uint32_t t = t0;
+    uint32_t slot = uni(find_slot(w.list[L], nslots, t));
+    SegEntry seg = uni(w.list[L][slot]);
+    uint32_t seg_end = uni(seg_tile_end(w.list[L], slot, nslots, ntiles));
+    bool loaded = false;
+    while (t < t1) {
+        if (!loaded) {
+            // entering a segment: skip it if it does not move, else start its piece
+            if ((seg.info >> 16) & SEG_SKIP) {
+                t = seg_end;
+                if (t >= t1) break;
+                ++slot;
+                seg = uni(w.list[L][slot]);
+                seg_end = uni(seg_tile_end(w.list[L], slot, nslots, ntiles));
+                continue;
+            }
+            if (threadIdx.x < R)
+                S.run[threadIdx.x] = w.bases[L][(size_t)slot * R + threadIdx.x] + w.pcnt[(size_t)t * R + threadIdx.x];
+            load_tile<KB, BT, ITEMS, PAY>(w, seg, t, key, pay);
+            loaded = true;
+        }
+        const uint32_t tn = t + 1;
+        const bool pref = tn < t1 && tn < seg_end;
+        if (pref) load_tile<KB, BT, ITEMS, PAY>(w, seg, tn, keyn, payn);
+        if (seg.len - (t - seg.tile_start) * TILE >= TILE)
+            scatter_tile<KB, K, BT, ITEMS, PAY, false, true>(w, L, S, seg, t, slot, key, pay);
+        else
+            scatter_tile<KB, K, BT, ITEMS, PAY, false, false>(w, L, S, seg, t, slot, key, pay);
+        t = tn;
+        if (pref) {
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) {
+                key[j] = keyn[j];
+                if (PAY) pay[j] = payn[j];
+            }
+        } else if (t < t1) {
+            ++slot;
+            seg = uni(w.list[L][slot]);
+            seg_end = uni(seg_tile_end(w.list[L], slot, nslots, ntiles));
+            loaded = false;
+        }
     }
 }
 
 // ----------------------------------------------------------------- k_finish
-// One workgroup per small segment (at most THREADS * ITEMS keys): find the
-// bits that vary inside it (AND/OR), sort stably by them with
+// One workgroup per small segment (at most BT * ITEMS keys): find the bits
+// that vary inside it (AND/OR), sort stably by them with
 // least-significant-first LDS passes of up to 8 bits, write to A.
-template <int KB, int ITEMS, bool PAY>
-__global__ __launch_bounds__(THREADS) void k_finish(Work w, int cls) {
+template <int KB, int BT, int ITEMS, bool PAY>
+struct FinishLds {
+    using V = typename KeyT<KB>::V;
+    static constexpr int R = 256;
+    static constexpr int CAP = BT * ITEMS;
+    static constexpr int NW = BT / WAVE;
+    V keys[CAP];
+    uint32_t pay[PAY ? CAP : 1];
+    unsigned long long tbl[NW][1][R];
+    uint32_t wh[NW][R];
+    uint32_t tmp[NW];
+    unsigned long long ao[NW][4];
+};
+
+template <int KB, int BT, int ITEMS, bool PAY>
+__global__ __launch_bounds__(BT) void k_finish(Work w, int cls) {
     using KT = KeyT<KB>;
     using V = typename KT::V;
     constexpr int KL = 8;
     constexpr int R = 1 << KL;
-    constexpr int CAP = THREADS * ITEMS;
-    constexpr int NB = KT::NBITS;
-    __shared__ V s_keys[CAP];
-    __shared__ uint32_t s_pay[PAY ? CAP : 1];
-    __shared__ uint32_t s_wh[WAVES][R];
-    __shared__ uint32_t s_dstart[R];
-    __shared__ uint32_t s_tmp[WAVES];
-    __shared__ unsigned long long s_ao[WAVES][4];
+    constexpr int CAP = BT * ITEMS;
+    constexpr int NW = BT / WAVE;
+    const int NB = (int)w.nbits;
+    __shared__ FinishLds<KB, BT, ITEMS, PAY> S;
 
     Ctl *ctl = w.ctl;
     if (ctl->error | ctl->overflow) return;
     const uint32_t nfin = min(ctl->fin_ctr[cls], w.max_fin[cls]);
     const int wv = threadIdx.x / WAVE, lane = lane_id();
     const uint32_t ebase = (uint32_t)wv * ITEMS * WAVE + (uint32_t)lane;
+    for (int i = threadIdx.x; i < NW * R; i += BT) (&S.wh[0][0])[i] = 0u;
+    for (int i = threadIdx.x; i < NW * R; i += BT) (&S.tbl[0][0][0])[i] = 0ull;
+    __syncthreads();
 
     for (uint32_t f = blockIdx.x; f < nfin; f += gridDim.x) {
-        const FinEntry fe = w.fin[cls][f];
+        const FinEntry fe = uni(w.fin[cls][f]);
         const uint32_t len = fe.info & 0xFFFFu;
         const int bitpos = (int)((fe.info >> 16) & 0xFFu);
         const uint32_t parity = (fe.info >> 24) & 1u;
-        const void *src = w.keys[parity];
-        const uint32_t *psrc = w.pay[parity];
-        const size_t gbase = fe.begin;
         if (len > (uint32_t)CAP || (size_t)fe.begin + len > w.n_total) {
             if (threadIdx.x == 0) atomicOr(&ctl->error, ERR_INTERNAL);
             continue;
         }
         if (threadIdx.x == 0) {
-            atomicAdd(&ctl->fin_keys, (unsigned long long)len);
-            atomicAdd(&ctl->fin_segs, 1ull);
+            atomicAdd(&ctl->fin_keys[cls], (unsigned long long)len);
+            atomicAdd(&ctl->fin_segs[cls], 1ull);
         }
+        const char *src = static_cast<const char *>(w.keys[parity]) + (size_t)fe.begin * KB;
+        const uint32_t *psrc = PAY ? w.pay[parity] + fe.begin : nullptr;
 
-        V key[ITEMS];
-        uint32_t pay[ITEMS];
+        // load into LDS in input order, AND/OR on the way
         V a = KT::ones(), o = KT::zero();
-#pragma unroll
-        for (int j = 0; j < ITEMS; ++j) {
-            const uint32_t e = ebase + j * WAVE;
-            key[j] = (e < len) ? KT::load(src, gbase + e) : KT::zero();
-            if (PAY) pay[j] = (e < len) ? psrc[gbase + e] : 0u;
-            if (e < len) {
-                a = KT::vand(a, key[j]);
-                o = KT::vor(o, key[j]);
-            }
+        for (uint32_t p = threadIdx.x; p < len; p += BT) {
+            const V k = KT::load(src, p);
+            S.keys[p] = k;
+            if (PAY) S.pay[p] = psrc[p];
+            a = KT::vand(a, k);
+            o = KT::vor(o, k);
         }
         Canon ca = KT::canon(a), co = KT::canon(o);
 #pragma unroll
@@ -640,100 +1005,87 @@ __global__ __launch_bounds__(THREADS) void k_finish(Work w, int cls) {
             co.lo |= __shfl_xor(co.lo, off, WAVE);
         }
         if (lane == 0) {
-            s_ao[wv][0] = ca.hi;
-            s_ao[wv][1] = ca.lo;
-            s_ao[wv][2] = co.hi;
-            s_ao[wv][3] = co.lo;
+            S.ao[wv][0] = ca.hi;
+            S.ao[wv][1] = ca.lo;
+            S.ao[wv][2] = co.hi;
+            S.ao[wv][3] = co.lo;
         }
         __syncthreads();
         Canon diff{0ull, 0ull};
         {
             unsigned long long ah = ~0ull, al = ~0ull, oh = 0ull, ol = 0ull;
 #pragma unroll
-            for (int q = 0; q < WAVES; ++q) {
-                ah &= s_ao[q][0];
-                al &= s_ao[q][1];
-                oh |= s_ao[q][2];
-                ol |= s_ao[q][3];
+            for (int q = 0; q < NW; ++q) {
+                ah &= S.ao[q][0];
+                al &= S.ao[q][1];
+                oh |= S.ao[q][2];
+                ol |= S.ao[q][3];
             }
             diff.hi = ah ^ oh;
             diff.lo = al ^ ol;
         }
-        __syncthreads();
-
         int hib = last_set_below(diff, bitpos, NB);
-        bool staged = false;  // true when the sorted order sits in LDS
+        if (hib < bitpos && parity == 0u) {
+            // nothing varies and the keys already sit in A: nothing to write
+            __syncthreads();
+            continue;
+        }
+        // least-significant window first; the order lives in S between passes
         while (hib >= bitpos) {
             const int lo = max(bitpos, hib - KL + 1);
             const int wbits = hib - lo + 1;
-            if (staged) {
-                // reload the previous pass's order into registers
-#pragma unroll
-                for (int j = 0; j < ITEMS; ++j) {
-                    const uint32_t e = ebase + j * WAVE;
-                    if (e < len) {
-                        key[j] = s_keys[e];
-                        if (PAY) pay[j] = s_pay[e];
-                    }
-                }
-            }
-            for (int i = threadIdx.x; i < WAVES * R; i += THREADS) (&s_wh[0][0])[i] = 0u;
-            __syncthreads();
-            uint32_t rnk[ITEMS];
+            V key[ITEMS];
+            uint32_t dg[ITEMS], rnk[ITEMS];
 #pragma unroll
             for (int j = 0; j < ITEMS; ++j) {
                 const uint32_t e = ebase + j * WAVE;
-                const bool valid = e < len;
-                const uint32_t dg = valid ? KT::digit(key[j], lo, wbits) : 0u;
-                uint32_t r, c;
-                wave_match<KL>(dg, valid, r, c);
-                uint32_t before = 0;
-                if (valid) before = s_wh[wv][dg];
-                rnk[j] = before + r;
-                if (valid && r + 1 == c) s_wh[wv][dg] = before + c;
+                key[j] = (e < len) ? S.keys[e] : KT::zero();
+                dg[j] = KT::digit(key[j], lo, wbits);
+            }
+            wave_rank<R, 1, ITEMS, false>(dg, ebase, len, &S.tbl[wv][0][0], &S.wh[wv][0], rnk);
+            uint32_t pay[ITEMS];
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) {
+                const uint32_t e = ebase + j * WAVE;
+                if (PAY) pay[j] = (e < len) ? S.pay[e] : 0u;
             }
             __syncthreads();
             uint32_t tcnt = 0;
             if (threadIdx.x < R) {
 #pragma unroll
-                for (int q = 0; q < WAVES; ++q) {
-                    const uint32_t x = s_wh[q][threadIdx.x];
-                    s_wh[q][threadIdx.x] = tcnt;
-                    tcnt += x;
-                }
+                for (int q = 0; q < NW; ++q) tcnt += S.wh[q][threadIdx.x];
             }
             uint32_t tot;
-            const uint32_t ds = block_excl_scan(tcnt, s_tmp, &tot);
-            if (threadIdx.x < R) s_dstart[threadIdx.x] = ds;
+            uint32_t acc = block_excl_scan<BT>(tcnt, S.tmp, &tot);  // every thread: it holds barriers
+            if (threadIdx.x < R) {
+#pragma unroll
+                for (int q = 0; q < NW; ++q) {
+                    const uint32_t x = S.wh[q][threadIdx.x];
+                    S.wh[q][threadIdx.x] = acc;
+                    acc += x;
+                }
+            }
             __syncthreads();
 #pragma unroll
             for (int j = 0; j < ITEMS; ++j) {
                 const uint32_t e = ebase + j * WAVE;
                 if (e < len) {
-                    const uint32_t dg = KT::digit(key[j], lo, wbits);
-                    const uint32_t pos = s_dstart[dg] + s_wh[wv][dg] + rnk[j];
-                    s_keys[pos] = key[j];
-                    if (PAY) s_pay[pos] = pay[j];
+                    const uint32_t pos = S.wh[wv][dg[j]] + rnk[j];
+                    S.keys[pos] = key[j];
+                    if (PAY) S.pay[pos] = pay[j];
                 }
             }
             __syncthreads();
-            staged = true;
+            // each wave clears its own counters: only it touches them before
+            // the next barrier
+            for (int i = lane; i < R; i += WAVE) S.wh[wv][i] = 0u;
             hib = last_set_below(diff, bitpos, lo);
         }
-        if (staged) {
-            for (uint32_t p = threadIdx.x; p < len; p += THREADS) {
-                KT::store(w.keys[0], gbase + p, s_keys[p]);
-                if (PAY) w.pay[0][gbase + p] = s_pay[p];
-            }
-        } else if (parity == 1u) {
-#pragma unroll
-            for (int j = 0; j < ITEMS; ++j) {
-                const uint32_t e = ebase + j * WAVE;
-                if (e < len) {
-                    KT::store(w.keys[0], gbase + e, key[j]);
-                    if (PAY) w.pay[0][gbase + e] = pay[j];
-                }
-            }
+        char *dst = static_cast<char *>(w.keys[0]) + (size_t)fe.begin * KB;
+        uint32_t *pdst = PAY ? w.pay[0] + fe.begin : nullptr;
+        for (uint32_t p = threadIdx.x; p < len; p += BT) {
+            KT::store(dst, p, S.keys[p]);
+            if (PAY) pdst[p] = S.pay[p];
         }
         __syncthreads();
     }

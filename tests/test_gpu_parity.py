@@ -19,9 +19,9 @@ def iota(n):
     return np.arange(n, dtype=np.uint32)
 
 
-def P(k=0, tile=0, T=0):
+def P(k=0, tile=0, T=0, offsets=0):
     from paper_0811_3448_amd import Params
-    return Params(digit_bits=k, tile_keys=tile, finish_max=T)
+    return Params(digit_bits=k, tile_keys=tile, finish_max=T, offsets=offsets)
 
 
 def compare(keys, with_payload=True, params=None):
@@ -60,15 +60,25 @@ def test_u32_distributions(dist):
     compare(keys)
 
 
+@pytest.mark.parametrize("offsets", [1, 2])
 @pytest.mark.parametrize("k,tile,T", [(8, 4096, 64), (8, 2048, 300), (4, 4096, 100), (4, 2048, 1000),
                                       (1, 4096, 64), (1, 2048, 5000), (8, 4096, 1)])
-def test_u32_global_passes(k, tile, T):
+def test_u32_global_passes(k, tile, T, offsets):
     """Small LDS threshold: many tiles per segment, several global passes,
-    look-back across tiles, ragged last tiles."""
+    chunk prefixes or look-back across tiles, ragged last tiles."""
     n = 100_003
-    compare(workloads.u32_uniform(n, 20 + k), params=P(k, tile, T))
-    compare(workloads.u32_and4(n, 21 + k), params=P(k, tile, T))
-    compare(workloads.u32_dup(n, 22 + k, 256), params=P(k, tile, T))
+    compare(workloads.u32_uniform(n, 20 + k), params=P(k, tile, T, offsets))
+    compare(workloads.u32_and4(n, 21 + k), params=P(k, tile, T, offsets))
+    compare(workloads.u32_dup(n, 22 + k, 256), params=P(k, tile, T, offsets))
+
+
+@pytest.mark.parametrize("offsets", [1, 2])
+def test_u32_many_chunks(offsets):
+    """Several million keys: every chunk holds many tiles, pieces of many
+    segments, both offset schemes."""
+    n = 3_000_017
+    compare(workloads.u32_uniform(n, 90), params=P(offsets=offsets))
+    compare(workloads.u32_and4(n, 91), params=P(T=2000, offsets=offsets))
 
 
 @pytest.mark.parametrize("dist", ["uniform", "nearly", "zipf", "dup"])
