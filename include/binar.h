@@ -68,7 +68,8 @@ extern "C" {
 /* Tuning knobs; a zero field means "library default".
  *   digit_bits : bits taken per global pass: 1, 4 or 8 (1 = the paper's
  *                binary partition step, made stable).
- *   tile_keys  : keys per scatter tile: 2048, 4096 or (digit_bits 8) 8192.
+ *   tile_keys  : keys per scatter tile: 2048, 4096 or (4-byte keys, digit_bits 8)
+ *                8192.
  *   finish_max : largest sub-array finished in on-chip memory (LDS) by one
  *                workgroup; capped by the key width's largest LDS class.
  *   offsets    : how a scatter tile finds where its keys go:

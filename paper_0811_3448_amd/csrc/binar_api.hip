@@ -394,8 +394,8 @@ int dispatch_k(const Resolved &r, const Work &w, const Layout &L, const uint32_t
     if (r.k == KK && r.tile == TT)                                          \
         return r.lookback ? enqueue<KB, KK, TT, PAY, true>(w, L, so, ns, n, st) \
                           : enqueue<KB, KK, TT, PAY, false>(w, L, so, ns, n, st);
-    if constexpr (KB <= 8) {
-        BINAR_CASE(8, 8192)  // 8192 16-byte keys do not fit in LDS
+    if constexpr (KB == 4) {
+        BINAR_CASE(8, 8192)  // wider keys: 8192 of them do not fit in LDS
     }
     BINAR_CASE(8, 4096)
     BINAR_CASE(8, 2048)

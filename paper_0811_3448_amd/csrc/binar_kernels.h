@@ -679,19 +679,34 @@ __global__ __launch_bounds__(THREADS) void k_copyback(Work w) {
 //     advancing by each tile's counts;
 //   LOOKBACK = true: tiles are taken in ticket order and each looks back over
 //     the earlier tiles of its segment (decoupled look-back).
-template <int KB, int K, int BT, int ITEMS, bool PAY>
+// Chunked scatter writes whole aligned bursts of BURST_BYTES of keys: the
+// part of each digit's run that does not yet fill a burst is carried in LDS
+// to the block's next tile (a partial burst costs the memory a
+// read-modify-write).  Only the first and last burst of a digit's run in a
+// piece can be partial.
+constexpr int BURST_BYTES = 64;
+
+template <int KB, int K, int BT, int ITEMS, bool PAY, bool LOOKBACK>
 struct ScatterLds {
     using V = typename KeyT<KB>::V;
     static constexpr int R = 1 << K;
     static constexpr int TILE = BT * ITEMS;
     static constexpr int NW = BT / WAVE;
-    static constexpr int P = NW >= 16 ? 1 : 2;  // lane-mask tables per wave (LDS budget)
+    static constexpr int P = 1;                      // lane-mask tables per wave
+    static constexpr int CB = BURST_BYTES / KB;      // keys per burst
+    static constexpr int CR = LOOKBACK ? 1 : R;      // digits that carry
     V keys[TILE];
     uint32_t pay[PAY ? TILE : 1];
     unsigned long long tbl[NW][P][R];  // lane masks of the wave ranking
     uint32_t wh[NW][R];             // per-wave digit counts -> staged offset of (wave, digit)
     uint32_t gofs[R];               // global index of staged position 0 of digit d
     uint32_t run[R];                // chunked offsets: next global index of digit d in this piece
+    uint32_t wlim[CR];              // staged keys below this global index are written now
+    uint32_t cc[CR];                // carried keys of digit d (global [run - cc, run))
+    uint32_t ccw[CR];               // carried keys written this tile, from global index clo
+    uint32_t clo[CR];
+    V ckeys[CR][CB];
+    uint32_t cpay[PAY ? CR : 1][CB];
     uint32_t tmp[NW];
     uint32_t tile, slot;
 };
@@ -728,7 +743,7 @@ __device__ __forceinline__ void load_tile(const Work &w, const SegEntry &seg, ui
 
 // Rank, offsets, stage and write one tile whose keys are in registers.
 template <int KB, int K, int BT, int ITEMS, bool PAY, bool LOOKBACK, bool FULL>
-__device__ __forceinline__ void scatter_tile(const Work &w, int L, ScatterLds<KB, K, BT, ITEMS, PAY> &S,
+__device__ __forceinline__ void scatter_tile(const Work &w, int L, ScatterLds<KB, K, BT, ITEMS, PAY, LOOKBACK> &S,
                                              const SegEntry &seg, uint32_t t, uint32_t slot,
                                              const typename KeyT<KB>::V (&key)[ITEMS], const uint32_t (&pay)[ITEMS]) {
     using KT = KeyT<KB>;
@@ -751,8 +766,7 @@ __device__ __forceinline__ void scatter_tile(const Work &w, int L, ScatterLds<KB
     const uint32_t ebase = (uint32_t)wv * ITEMS * WAVE + (uint32_t)lane;
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) dg[j] = KT::digit(key[j], bitpos, wbits);
-    wave_rank<R, ScatterLds<KB, K, BT, ITEMS, PAY>::P, ITEMS, FULL>(dg, ebase, tlen, &S.tbl[wv][0][0], &S.wh[wv][0],
-                                                                     rnk);
+    wave_rank<R, 1, ITEMS, FULL>(dg, ebase, tlen, &S.tbl[wv][0][0], &S.wh[wv][0], rnk);
     __syncthreads();
     // per digit: staged offset of each wave's keys, tile count, global offset
     uint32_t tcnt = 0;
@@ -799,8 +813,21 @@ __device__ __forceinline__ void scatter_tile(const Work &w, int L, ScatterLds<KB
             }
             if (tcnt) S.gofs[threadIdx.x] = w.bases[L][(size_t)slot * R + threadIdx.x] + excl - dstart;
         } else {
-            S.gofs[threadIdx.x] = S.run[threadIdx.x] - dstart;
-            S.run[threadIdx.x] += tcnt;
+            // the run of digit d so far: carried [gpos - cc, gpos) + this tile's
+            // [gpos, gpos + tcnt); write everything below the last burst
+            // boundary, carry the rest
+            constexpr uint32_t CB = ScatterLds<KB, K, BT, ITEMS, PAY, LOOKBACK>::CB;
+            const uint32_t gpos = S.run[threadIdx.x];
+            const uint32_t cc = S.cc[threadIdx.x];
+            const uint32_t lo = gpos - cc, hi = gpos + tcnt;
+            const uint32_t cut = hi & ~(CB - 1u);
+            const uint32_t wlim = cut > lo ? cut : lo;
+            S.gofs[threadIdx.x] = gpos - dstart;
+            S.wlim[threadIdx.x] = wlim;
+            S.ccw[threadIdx.x] = cut > lo ? cc : 0u;
+            S.clo[threadIdx.x] = lo;
+            S.cc[threadIdx.x] = hi - wlim;
+            S.run[threadIdx.x] = hi;
         }
     }
     __syncthreads();
@@ -814,6 +841,22 @@ __device__ __forceinline__ void scatter_tile(const Work &w, int L, ScatterLds<KB
             if (PAY) S.pay[pos] = pay[j];
         }
     }
+    if (!LOOKBACK) {
+        // carried keys whose burst this tile completes
+        constexpr int CB = ScatterLds<KB, K, BT, ITEMS, PAY, LOOKBACK>::CB;
+        for (int i = threadIdx.x; i < R * CB; i += BT) {
+            const int d = i / CB, k = i % CB;
+            if ((uint32_t)k < S.ccw[d]) {
+                const uint32_t g = S.clo[d] + k;
+                if (g < w.n_total) {
+                    KT::store(dst, g, S.ckeys[d][k]);
+                    if (PAY) pdst[g] = S.cpay[d][k];
+                } else {
+                    atomicOr(&ctl->error, ERR_INTERNAL);
+                }
+            }
+        }
+    }
     __syncthreads();
     // coalesced write: consecutive staged keys of one digit go to consecutive
     // global positions; each wave clears its own counters for the next tile
@@ -823,12 +866,42 @@ __device__ __forceinline__ void scatter_tile(const Work &w, int L, ScatterLds<KB
         const uint32_t p = j * BT + threadIdx.x;
         if (FULL || p < tlen) {
             const V k = S.keys[p];
-            const uint32_t g = S.gofs[KT::digit(k, bitpos, wbits)] + p;
-            if (g < w.n_total) {
+            const uint32_t d = KT::digit(k, bitpos, wbits);
+            const uint32_t g = S.gofs[d] + p;
+            if (!LOOKBACK && g >= S.wlim[d]) {
+                // does not fill a burst yet: carry it to the next tile
+                S.ckeys[d][g - S.wlim[d]] = k;
+                if (PAY) S.cpay[d][g - S.wlim[d]] = S.pay[p];
+            } else if (g < w.n_total) {
                 KT::store(dst, g, k);
                 if (PAY) pdst[g] = S.pay[p];
             } else {
                 atomicOr(&ctl->error, ERR_INTERNAL);
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// End of a piece in the chunked scatter: write the carried keys of every
+// digit (the partial last burst of each run).
+template <int KB, int K, int BT, int ITEMS, bool PAY>
+__device__ __forceinline__ void flush_carry(const Work &w, ScatterLds<KB, K, BT, ITEMS, PAY, false> &S,
+                                            uint32_t parity) {
+    using KT = KeyT<KB>;
+    constexpr int R = 1 << K;
+    constexpr int CB = ScatterLds<KB, K, BT, ITEMS, PAY, false>::CB;
+    void *dst = w.keys[parity ^ 1u];
+    uint32_t *pdst = w.pay[parity ^ 1u];
+    for (int i = threadIdx.x; i < R * CB; i += BT) {
+        const int d = i / CB, k = i % CB;
+        if ((uint32_t)k < S.cc[d]) {
+            const uint32_t g = S.run[d] - S.cc[d] + k;
+            if (g < w.n_total) {
+                KT::store(dst, g, S.ckeys[d][k]);
+                if (PAY) pdst[g] = S.cpay[d][k];
+            } else {
+                atomicOr(&w.ctl->error, ERR_INTERNAL);
             }
         }
     }
@@ -841,7 +914,7 @@ __global__ __launch_bounds__(BT) void k_scatter(Work w, int L) {
     constexpr int R = 1 << K;
     constexpr uint32_t TILE = BT * ITEMS;
     constexpr int NW = BT / WAVE;
-    __shared__ ScatterLds<KB, K, BT, ITEMS, PAY> S;
+    __shared__ ScatterLds<KB, K, BT, ITEMS, PAY, LOOKBACK> S;
 
     Ctl *ctl = w.ctl;
     if (ctl->error | ctl->overflow) return;
@@ -856,12 +929,12 @@ __global__ __launch_bounds__(BT) void k_scatter(Work w, int L) {
         if (t0 >= t1) return;
     }
     for (int i = threadIdx.x; i < NW * R; i += BT) (&S.wh[0][0])[i] = 0u;
-    for (int i = threadIdx.x; i < NW * ScatterLds<KB, K, BT, ITEMS, PAY>::P * R; i += BT) (&S.tbl[0][0][0])[i] = 0ull;
+    for (int i = threadIdx.x; i < NW * R; i += BT) (&S.tbl[0][0][0])[i] = 0ull;
     __syncthreads();
 
     V key[ITEMS];
     uint32_t pay[ITEMS];
-    if (LOOKBACK) {
+    if constexpr (LOOKBACK) {
         // tiles in ticket order; each looks back over its segment's earlier tiles
         for (;;) {
             if (threadIdx.x == 0) {
@@ -882,9 +955,7 @@ __global__ __launch_bounds__(BT) void k_scatter(Work w, int L) {
             else
                 scatter_tile<KB, K, BT, ITEMS, PAY, true, false>(w, L, S, seg, t, slot, key, pay);
         }
-        return;
-    }
-
+    } else {
     // chunked: walk tiles t0 .. t1 in order; the next tile of the same segment
     // is loaded into a second register set while the current one is processed
     V keyn[ITEMS];
@@ -905,8 +976,10 @@ __global__ __launch_bounds__(BT) void k_scatter(Work w, int L) {
                 seg_end = uni(seg_tile_end(w.list[L], slot, nslots, ntiles));
                 continue;
             }
-            if (threadIdx.x < R)
+            if (threadIdx.x < R) {
                 S.run[threadIdx.x] = w.bases[L][(size_t)slot * R + threadIdx.x] + w.pcnt[(size_t)t * R + threadIdx.x];
+                S.cc[threadIdx.x] = 0u;
+            }
             load_tile<KB, BT, ITEMS, PAY>(w, seg, t, key, pay);
             loaded = true;
         }
@@ -924,12 +997,17 @@ __global__ __launch_bounds__(BT) void k_scatter(Work w, int L) {
                 key[j] = keyn[j];
                 if (PAY) pay[j] = payn[j];
             }
-        } else if (t < t1) {
+        } else {
+            // the piece ends here
+            flush_carry<KB, K, BT, ITEMS, PAY>(w, S, (seg.info >> 8) & 1u);
+        }
+        if (!pref && t < t1) {
             ++slot;
             seg = uni(w.list[L][slot]);
             seg_end = uni(seg_tile_end(w.list[L], slot, nslots, ntiles));
             loaded = false;
         }
+    }
     }
 }
 
