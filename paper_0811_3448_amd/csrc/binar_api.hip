@@ -29,6 +29,9 @@ size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
 // LDS-finish classes: a block of FIN_BT threads, keys per thread of each
 // class, per key width (largest class: 8192 keys, 5120 for 16-byte keys).
 constexpr int FIN_BT = 256;
+// The digit count streams keys at full bandwidth: big blocks, so that even one
+// block per CU (the 8192-key tile grid) keeps enough loads in flight.
+constexpr int HIST_BT = 1024;
 template <int KB>
 struct FinItems;
 template <>
@@ -100,11 +103,12 @@ int resolve(uint32_t kb, bool pay, const binar_params *p, Resolved *r) {
         if (p->offsets) d.offsets = p->offsets;
     }
     if (!d.digit_bits) d.digit_bits = 8;
-    if (!d.tile_keys) d.tile_keys = 4096;
+    if (!d.tile_keys) d.tile_keys = (kb == 4 && d.digit_bits == 8) ? 8192 : 4096;
     if (!d.offsets) d.offsets = 1;
     const uint32_t tmax = fin_cap(kb, NCLASS - 1);
     if (!d.finish_max) d.finish_max = tmax;
     if (!supported_k(d.digit_bits) || !supported_tile(d.tile_keys) || d.offsets > 2) return BINAR_EINVAL;
+    if (d.tile_keys == 8192 && (kb != 4 || d.digit_bits != 8)) return BINAR_EINVAL;
     const uint32_t nbits = (p && p->key_bits) ? p->key_bits : 8u * kb;
     if (nbits > 8u * kb) return BINAR_EINVAL;
     r->nbits = nbits;
@@ -338,7 +342,7 @@ int enqueue(Work w, const Layout &L, const uint32_t *seg_off, uint32_t nseg, uin
         const int Lc = j & 1;
         {
             Timed tm(st, "k_hist", j);
-            hipLaunchKernelGGL((k_hist<KB, K, LB>), dim3(hg), dim3(THREADS), 0, st, w, Lc);
+            hipLaunchKernelGGL((k_hist<KB, K, LB, HIST_BT>), dim3(hg), dim3(HIST_BT), 0, st, w, Lc);
         }
         {
             Timed tm(st, "k_pscan", j);

@@ -361,15 +361,16 @@ __device__ __forceinline__ void load_vec(const void *p, size_t i, typename KeyT<
 // Also resets the next list and the scatter ticket (nothing else touches
 // them during this kernel) and, for the look-back scatter, clears the
 // look-back words of every tile.
-template <int KB, int K, bool LOOKBACK>
-__global__ __launch_bounds__(THREADS) void k_hist(Work w, int L) {
+template <int KB, int K, bool LOOKBACK, int BT>
+__global__ __launch_bounds__(BT) void k_hist(Work w, int L) {
     using KT = KeyT<KB>;
     using V = typename KT::V;
     constexpr int R = 1 << K;
     constexpr int VN = Vec<KB>::N;
     constexpr int U = 4;  // vectors in flight per thread
-    __shared__ uint32_t s_h[WAVES][R];
-    __shared__ unsigned long long s_ao[WAVES][4];
+    constexpr int NW = BT / WAVE;
+    __shared__ uint32_t s_h[NW][R];
+    __shared__ unsigned long long s_ao[NW][4];
 
     Ctl *ctl = w.ctl;
     if (ctl->error | ctl->overflow) return;
@@ -386,9 +387,9 @@ __global__ __launch_bounds__(THREADS) void k_hist(Work w, int L) {
     if (t0 >= t1) return;
 
     const int wv = threadIdx.x / WAVE, lane = lane_id();
-    for (int i = threadIdx.x; i < WAVES * R; i += THREADS) (&s_h[0][0])[i] = 0u;
+    for (int i = threadIdx.x; i < NW * R; i += BT) (&s_h[0][0])[i] = 0u;
     if (LOOKBACK)
-        for (size_t i = (size_t)t0 * R + threadIdx.x; i < (size_t)t1 * R; i += THREADS) w.status[i] = 0u;
+        for (size_t i = (size_t)t0 * R + threadIdx.x; i < (size_t)t1 * R; i += BT) w.status[i] = 0u;
     __syncthreads();
 
     uint32_t slot = find_slot(w.list[L], nslots, t0);
@@ -406,28 +407,28 @@ __global__ __launch_bounds__(THREADS) void k_hist(Work w, int L) {
         const size_t mis = ((16u - (reinterpret_cast<uintptr_t>(src) & 15u)) & 15u) / KB;
         const size_t b0 = min(g1, g0 + ((mis + VN - (g0 % VN)) % VN));
         const size_t b1 = b0 + (g1 - b0) / VN * VN;
-        for (size_t i = g0 + threadIdx.x; i < b0; i += THREADS) {
+        for (size_t i = g0 + threadIdx.x; i < b0; i += BT) {
             const V v = KT::load(src, i);
             atomicAdd(&s_h[wv][KT::digit(v, bitpos, wbits)], 1u);
             a = KT::vand(a, v);
             o = KT::vor(o, v);
         }
-        for (size_t i = b1 + threadIdx.x; i < g1; i += THREADS) {
+        for (size_t i = b1 + threadIdx.x; i < g1; i += BT) {
             const V v = KT::load(src, i);
             atomicAdd(&s_h[wv][KT::digit(v, bitpos, wbits)], 1u);
             a = KT::vand(a, v);
             o = KT::vor(o, v);
         }
-        for (size_t i = b0 + (size_t)threadIdx.x * VN; i < b1; i += (size_t)THREADS * VN * U) {
+        for (size_t i = b0 + (size_t)threadIdx.x * VN; i < b1; i += (size_t)BT * VN * U) {
             V v[U][VN];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const size_t x = i + (size_t)u * THREADS * VN;
+                const size_t x = i + (size_t)u * BT * VN;
                 if (x < b1) load_vec<KB>(src, x, v[u]);
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const size_t x = i + (size_t)u * THREADS * VN;
+                const size_t x = i + (size_t)u * BT * VN;
                 if (x < b1) {
 #pragma unroll
                     for (int q = 0; q < VN; ++q) {
@@ -455,10 +456,10 @@ __global__ __launch_bounds__(THREADS) void k_hist(Work w, int L) {
         }
         __syncthreads();
         uint32_t *row = w.pcnt + (size_t)t * R;
-        for (int d = threadIdx.x; d < R; d += THREADS) {
+        for (int d = threadIdx.x; d < R; d += BT) {
             uint32_t c = 0;
 #pragma unroll
-            for (int q = 0; q < WAVES; ++q) {
+            for (int q = 0; q < NW; ++q) {
                 c += s_h[q][d];
                 s_h[q][d] = 0u;
             }
@@ -466,7 +467,7 @@ __global__ __launch_bounds__(THREADS) void k_hist(Work w, int L) {
         }
         if (threadIdx.x < 4) {
             unsigned long long v = s_ao[0][threadIdx.x];
-            for (int q = 1; q < WAVES; ++q)
+            for (int q = 1; q < NW; ++q)
                 v = (threadIdx.x < 2) ? (v & s_ao[q][threadIdx.x]) : (v | s_ao[q][threadIdx.x]);
             unsigned long long *dst = w.andor[L] + (size_t)slot * 4 + threadIdx.x;
             if (threadIdx.x < 2)

@@ -74,4 +74,5 @@ def test_workspace_bytes(lib):
     assert binar.workspace_bytes(4, 1 << 30, True) == 0
     assert binar.workspace_bytes(16, 1000, True) > binar.workspace_bytes(4, 1000, True)
     p = binar.default_params(4, True)
-    assert p.digit_bits == 8 and p.tile_keys in (2048, 4096) and p.finish_max > 0
+    assert p.digit_bits == 8 and p.tile_keys in (2048, 4096, 8192) and p.finish_max > 0
+    assert binar.default_params(8, True).tile_keys in (2048, 4096)
