@@ -162,6 +162,32 @@ int binar_set_default_params(uint32_t key_bytes, int has_payload, const binar_pa
 int binar_profile_enable(int on);
 int binar_profile_read(binar_launch_time *out, uint32_t cap, uint32_t *count);
 
+/* A reusable plan for repeated sorts on resident buffers (batched or served
+ * work).  The plan owns a workspace for up to max_keys keys in up to
+ * max_segments segments.  The first binar_plan_sort with a given
+ * (keys, payload, seg_offsets, num_segments, n_total) captures the call's
+ * whole launch sequence into a HIP graph on a stream of the plan's own;
+ * later calls with the same values replay that graph on `stream`, whatever
+ * the buffers then hold (segment offsets are read on the device, so the
+ * segment layout may change between replays within the capacity).  Up to 16
+ * graphs are kept per plan.  With seg_offsets, keys and payload must hold
+ * max_keys entries (the offsets are checked on the device against max_keys
+ * and n_total is ignored), so one graph serves every batch placed in the
+ * same buffers.  seg_offsets may be NULL: one array of n_total keys (then
+ * n_total is part of the graph's identity).  Calls on one plan must not
+ * overlap in time.  binar_plan_stats reads
+ * the counters of the plan's last sort; binar_plan_graphs returns how many
+ * graphs the plan holds. */
+typedef struct binar_plan binar_plan;
+int binar_plan_create(binar_plan **out, uint32_t key_bytes, uint64_t max_keys, uint32_t max_segments,
+                      int has_payload, const binar_params *params);
+int binar_plan_sort(binar_plan *plan, void *keys, uint32_t *payload, const uint32_t *seg_offsets,
+                    uint32_t num_segments, uint64_t n_total, void *stream);
+int binar_plan_stats(binar_plan *plan, void *stream, binar_stats *out);
+int binar_plan_graphs(const binar_plan *plan);
+size_t binar_plan_workspace_bytes(const binar_plan *plan);
+void binar_plan_destroy(binar_plan *plan);
+
 /* Static description of a status code. */
 const char *binar_strerror(int status);
 

@@ -11,6 +11,7 @@ memory and streams, every step of the sort runs in the library's kernels.
 from .binar import (  # noqa: F401
     BinarError,
     Params,
+    Plan,
     Workspace,
     default_params,
     key_bytes_of,

@@ -51,11 +51,20 @@ def _load():
     L.binar_set_default_params.argtypes = [u32, i32, P]
     L.binar_profile_enable.argtypes = [i32]
     L.binar_profile_read.argtypes = [ctypes.POINTER(_LaunchTime), u32, ctypes.POINTER(u32)]
+    L.binar_plan_create.argtypes = [ctypes.POINTER(vp), u32, u64, u32, i32, P]
+    L.binar_plan_sort.argtypes = [vp, vp, vp, vp, u32, u64, vp]
+    L.binar_plan_stats.argtypes = [vp, vp, ctypes.POINTER(_Stats)]
+    L.binar_plan_graphs.argtypes = [vp]
+    L.binar_plan_workspace_bytes.argtypes = [vp]
+    L.binar_plan_workspace_bytes.restype = sz
+    L.binar_plan_destroy.argtypes = [vp]
+    L.binar_plan_destroy.restype = None
     L.binar_strerror.argtypes = [i32]
     L.binar_strerror.restype = ctypes.c_char_p
     for f in ("binar_sort", "binar_sort_async", "binar_sort_segmented", "binar_sort_ex",
               "binar_stats_read", "binar_get_default_params", "binar_set_default_params",
-              "binar_profile_enable", "binar_profile_read"):
+              "binar_profile_enable", "binar_profile_read", "binar_plan_create", "binar_plan_sort",
+              "binar_plan_stats", "binar_plan_graphs"):
         getattr(L, f).restype = i32
     return L
 
@@ -182,10 +191,7 @@ def stats(workspace: Workspace | None = None, stream=None) -> dict:
     s = _Stats()
     _check(lib.binar_stats_read(None if workspace is None else workspace.ptr, _stream_ptr(stream),
                                 ctypes.byref(s)))
-    return {"moved": list(s.moved), "hist_keys": list(s.hist_keys), "finish_keys": s.finish_keys,
-            "finish_segments": s.finish_segments, "passes": s.passes, "status": s.status,
-            "finish_class_keys": list(s.finish_class_keys),
-            "finish_class_segments": list(s.finish_class_segments), "copyback_keys": s.copyback_keys}
+    return _stats_dict(s)
 
 
 def profile_enable(on: bool = True) -> None:
@@ -199,6 +205,65 @@ def profile_read(cap: int = 1 << 16) -> list:
     cnt = ctypes.c_uint32(0)
     _check(lib.binar_profile_read(buf, cap, ctypes.byref(cnt)))
     return [(buf[i].name.decode(), buf[i].pass_, float(buf[i].ms)) for i in range(cnt.value)]
+
+
+def _stats_dict(s: "_Stats") -> dict:
+    return {"moved": list(s.moved), "hist_keys": list(s.hist_keys), "finish_keys": s.finish_keys,
+            "finish_segments": s.finish_segments, "passes": s.passes, "status": s.status,
+            "finish_class_keys": list(s.finish_class_keys),
+            "finish_class_segments": list(s.finish_class_segments), "copyback_keys": s.copyback_keys}
+
+
+class Plan:
+    """Reusable sort plan on resident buffers: the first sort with a given
+    set of buffers captures a HIP graph, later sorts replay it (see
+    binar_plan_* in binar.h)."""
+
+    def __init__(self, key_bytes: int, max_keys: int, max_segments: int = 1, has_payload: bool = True,
+                 params: Params | None = None):
+        self._h = ctypes.c_void_p()
+        pp = None if params is None else ctypes.byref(params.c())
+        _check(lib.binar_plan_create(ctypes.byref(self._h), key_bytes, max_keys, max_segments,
+                                     1 if has_payload else 0, pp))
+        self.key_bytes, self.max_keys, self.max_segments = key_bytes, max_keys, max_segments
+
+    def sort(self, keys, payload=None, seg_offsets=None, n_total: int | None = None, stream=None):
+        _check_tensors(keys, payload)
+        if key_bytes_of(keys) != self.key_bytes:
+            raise ValueError("key width differs from the plan's")
+        n = keys.shape[0] if n_total is None else n_total
+        nseg = 0
+        if seg_offsets is not None:
+            if not seg_offsets.is_cuda or seg_offsets.element_size() != 4 or not seg_offsets.is_contiguous():
+                raise ValueError("seg_offsets must be a contiguous 4-byte device tensor")
+            nseg = seg_offsets.shape[0] - 1
+        _check(lib.binar_plan_sort(self._h, _dev_ptr(keys), _dev_ptr(payload), _dev_ptr(seg_offsets), nseg, n,
+                                   _stream_ptr(stream)))
+        return keys
+
+    def stats(self, stream=None) -> dict:
+        s = _Stats()
+        _check(lib.binar_plan_stats(self._h, _stream_ptr(stream), ctypes.byref(s)))
+        return _stats_dict(s)
+
+    @property
+    def graphs(self) -> int:
+        return int(lib.binar_plan_graphs(self._h))
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(lib.binar_plan_workspace_bytes(self._h))
+
+    def close(self):
+        if self._h:
+            lib.binar_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def default_params(key_bytes: int, has_payload: bool) -> Params:

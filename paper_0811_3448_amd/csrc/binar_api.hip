@@ -284,12 +284,17 @@ struct Prof {
     }
 } g_prof;
 
+// Set while this thread captures a launch sequence into a graph: no timing
+// events are recorded into graphs.
+thread_local bool t_capturing = false;
+
 struct Timed {
     hipStream_t st;
     hipEvent_t a = nullptr, b = nullptr;
     const char *name;
     int pass;
     Timed(hipStream_t s, const char *n, int p) : st(s), name(n), pass(p) {
+        if (t_capturing) return;
         std::lock_guard<std::mutex> lk(g_prof.mu);
         if (!g_prof.on) return;
         a = g_prof.ev();
@@ -425,17 +430,22 @@ int dispatch(const Resolved &r, const Work &w, const Layout &L, const uint32_t *
     return BINAR_EINVAL;
 }
 
+int check_buffers(void *keys, uint32_t kb, uint32_t *payload) {
+    if (keys == nullptr) return BINAR_EINVAL;
+    if (kb == 16 && (reinterpret_cast<uintptr_t>(keys) & 15u)) return BINAR_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(keys) & 3u) || (reinterpret_cast<uintptr_t>(payload) & 3u))
+        return BINAR_EINVAL;
+    if (kb == 8 && (reinterpret_cast<uintptr_t>(keys) & 7u)) return BINAR_EINVAL;
+    return BINAR_OK;
+}
+
 int run(void *keys, uint32_t kb, uint64_t n, uint32_t *payload, const uint32_t *seg_off, uint32_t nseg,
         const binar_params *params, hipStream_t st, void *ws, size_t ws_bytes) {
     if (!valid_kb(kb)) return BINAR_EINVAL;
     if (n > BINAR_MAX_KEYS) return BINAR_ERANGE;
     if (seg_off == nullptr && n < 2) return BINAR_OK;  // base case: nothing to order
     if (seg_off != nullptr && nseg == 0) return BINAR_OK;
-    if (keys == nullptr) return BINAR_EINVAL;
-    if (kb == 16 && (reinterpret_cast<uintptr_t>(keys) & 15u)) return BINAR_EINVAL;
-    if ((reinterpret_cast<uintptr_t>(keys) & 3u) || (reinterpret_cast<uintptr_t>(payload) & 3u))
-        return BINAR_EINVAL;
-    if (kb == 8 && (reinterpret_cast<uintptr_t>(keys) & 7u)) return BINAR_EINVAL;
+    if (int rc = check_buffers(keys, kb, payload)) return rc;
     Resolved r;
     int rc = resolve(kb, payload != nullptr, params, &r);
     if (rc) return rc;
@@ -460,6 +470,138 @@ const void *last_ws(int dev) {
 
 }  // namespace
 }  // namespace binar
+
+// ------------------------------------------------------------------- plans
+struct binar_plan {
+    int dev = 0;
+    binar::Resolved r{};
+    binar::Layout L{};
+    uint64_t max_keys = 0;
+    uint32_t max_segments = 0;
+    void *ws = nullptr;
+    hipStream_t cap = nullptr;  // capture stream (never runs work)
+    struct Graph {
+        void *keys;
+        uint32_t *pay;
+        const uint32_t *off;
+        uint32_t nseg;
+        uint64_t n;
+        hipGraph_t g;
+        hipGraphExec_t ge;
+    };
+    std::vector<Graph> graphs;
+};
+
+namespace {
+void plan_free(binar_plan *p) {
+    for (auto &g : p->graphs) {
+        (void)hipGraphExecDestroy(g.ge);
+        (void)hipGraphDestroy(g.g);
+    }
+    p->graphs.clear();
+    if (p->cap) (void)hipStreamDestroy(p->cap);
+    if (p->ws) (void)hipFree(p->ws);
+    delete p;
+}
+}  // namespace
+
+extern "C" {
+
+int binar_plan_create(binar_plan **out, uint32_t key_bytes, uint64_t max_keys, uint32_t max_segments,
+                      int has_payload, const binar_params *params) {
+    using namespace binar;
+    if (!out) return BINAR_EINVAL;
+    *out = nullptr;
+    if (!valid_kb(key_bytes) || max_segments == 0) return BINAR_EINVAL;
+    if (max_keys > BINAR_MAX_KEYS) return BINAR_ERANGE;
+    binar_plan *p = new (std::nothrow) binar_plan();
+    if (!p) return BINAR_ENOMEM;
+    int rc = resolve(key_bytes, has_payload != 0, params, &p->r);
+    if (rc) {
+        delete p;
+        return rc;
+    }
+    p->max_keys = max_keys < 2 ? 2 : max_keys;
+    p->max_segments = max_segments;
+    p->L = make_layout(p->r, p->max_keys);
+    if (hipGetDevice(&p->dev) != hipSuccess) {
+        delete p;
+        return BINAR_EDEVICE;
+    }
+    if (hipMalloc(&p->ws, p->L.total) != hipSuccess) {
+        (void)hipGetLastError();
+        p->ws = nullptr;
+        plan_free(p);
+        return BINAR_ENOMEM;
+    }
+    if (hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess) {
+        plan_free(p);
+        return BINAR_EDEVICE;
+    }
+    *out = p;
+    return BINAR_OK;
+}
+
+int binar_plan_sort(binar_plan *p, void *keys, uint32_t *payload, const uint32_t *seg_offsets,
+                    uint32_t num_segments, uint64_t n_total, void *stream) {
+    using namespace binar;
+    if (!p) return BINAR_EINVAL;
+    if (n_total > p->max_keys) return BINAR_ERANGE;
+    if (seg_offsets ? (num_segments == 0 || num_segments > p->max_segments) : false) return BINAR_EINVAL;
+    if ((payload != nullptr) != p->r.pay) return BINAR_EINVAL;
+    if (!seg_offsets && n_total < 2) return BINAR_OK;
+    if (int rc = check_buffers(keys, p->r.kb, payload)) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const uint32_t nseg = seg_offsets ? num_segments : 1u;
+    // segmented: the buffers hold the plan's capacity and the device checks
+    // the offsets against it, so one graph serves every batch on them
+    if (seg_offsets) n_total = p->max_keys;
+    for (auto &g : p->graphs)
+        if (g.keys == keys && g.pay == payload && g.off == seg_offsets && g.nseg == nseg && g.n == n_total) {
+            note_ws(p->dev, p->ws);
+            return hipGraphLaunch(g.ge, st) == hipSuccess ? BINAR_OK : BINAR_EDEVICE;
+        }
+    // capture the launch sequence once for these buffers
+    Work w = make_work(p->L, p->r, static_cast<char *>(p->ws), keys, payload, (uint32_t)n_total);
+    if (hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return BINAR_EDEVICE;
+    t_capturing = true;
+    int rc = dispatch(p->r, w, p->L, seg_offsets, nseg, (uint32_t)n_total, p->cap);
+    t_capturing = false;
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(p->cap, &g);
+    if (rc || e != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc ? rc : BINAR_EDEVICE;
+    }
+    hipGraphExec_t ge = nullptr;
+    if (hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return BINAR_EDEVICE;
+    }
+    if (p->graphs.size() >= 16) {
+        (void)hipGraphExecDestroy(p->graphs.front().ge);
+        (void)hipGraphDestroy(p->graphs.front().g);
+        p->graphs.erase(p->graphs.begin());
+    }
+    p->graphs.push_back(binar_plan::Graph{keys, payload, seg_offsets, nseg, n_total, g, ge});
+    note_ws(p->dev, p->ws);
+    return hipGraphLaunch(ge, st) == hipSuccess ? BINAR_OK : BINAR_EDEVICE;
+}
+
+int binar_plan_stats(binar_plan *p, void *stream, binar_stats *out) {
+    if (!p) return BINAR_EINVAL;
+    return binar_stats_read(p->ws, stream, out);
+}
+
+int binar_plan_graphs(const binar_plan *p) { return p ? (int)p->graphs.size() : 0; }
+
+size_t binar_plan_workspace_bytes(const binar_plan *p) { return p ? p->L.total : 0; }
+
+void binar_plan_destroy(binar_plan *p) {
+    if (p) plan_free(p);
+}
+
+}  // extern "C"
 
 using namespace binar;
 

@@ -60,3 +60,27 @@ def check_sorted_permutation(keys_in, keys_out, pay_out):
     assert np.array_equal(keys_in[pay_out], keys_out), "keys do not follow payload"
     tie = keys_out[1:] == keys_out[:-1]
     assert np.all(pay_out[1:][tie] > pay_out[:-1][tie]), "unstable on ties"
+
+
+def check_segmented(keys_in, offsets, keys_out, pay_out):
+    """Complete check of per-segment stable sorts of unsigned integer keys
+    with a global-index payload: each segment's payload is a permutation of
+    its own indices, keys follow the payload, keys are nondecreasing inside
+    each segment and ties keep index order."""
+    offsets = np.asarray(offsets, dtype=np.int64)
+    n = int(offsets[-1])
+    if n == 0:
+        return
+    sizes = np.diff(offsets)
+    seg = np.repeat(np.arange(sizes.shape[0]), sizes)
+    p = pay_out[:n].astype(np.int64)
+    assert np.all(p >= offsets[seg]) and np.all(p < offsets[seg + 1]), "payload leaves its segment"
+    seen = np.zeros(n, dtype=bool)
+    seen[p] = True
+    assert seen.all(), "payload is not a permutation"
+    assert np.array_equal(keys_in[p], keys_out[:n]), "keys do not follow payload"
+    same = seg[1:] == seg[:-1]
+    k0, k1 = keys_out[:n - 1], keys_out[1:n]
+    assert np.all(k1[same] >= k0[same]), "not sorted inside a segment"
+    tie = same & (k1 == k0)
+    assert np.all(p[1:][tie] > p[:-1][tie]), "unstable on ties"
