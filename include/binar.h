@@ -66,10 +66,11 @@ extern "C" {
 #define BINAR_MAX_KEYS ((1u << 30) - 1u)
 
 /* Tuning knobs; a zero field means "library default".
- *   digit_bits : bits taken per global pass: 1, 4 or 8 (1 = the paper's
- *                binary partition step, made stable).
- *   tile_keys  : keys per scatter tile: 2048, 4096 or (4-byte keys, digit_bits 8)
- *                8192.
+ *   digit_bits : bits taken per global pass: 1, 4, 5, 6, 7 or 8 (1 = the
+ *                paper's binary partition step, made stable).
+ *   tile_keys  : keys per scatter tile: 4096 for every digit_bits; 2048 for
+ *                digit_bits 1, 4 and 8; 8192 for 4-byte keys with digit_bits 8.
+ *                Other pairs return BINAR_EINVAL.
  *   finish_max : largest sub-array finished in on-chip memory (LDS) by one
  *                workgroup; capped by the key width's largest LDS class.
  *   offsets    : how a scatter tile finds where its keys go:
@@ -150,9 +151,18 @@ size_t binar_workspace_bytes(uint32_t key_bytes, uint64_t n, int has_payload,
  * calling device's pool), after synchronising `stream`. */
 int binar_stats_read(const void *workspace, void *stream, binar_stats *out);
 
-/* The defaults binar_sort uses; set by the autotuner.  key_bytes 4, 8, 16. */
+/* The defaults a call uses for the zero fields of its params (all fields
+ * filled in, key_bits = 8 * key_bytes); key_bytes 4, 8, 16.  set replaces
+ * them (zero fields: built-in choice; key_bits is ignored) and returns
+ * BINAR_EINVAL, changing nothing, for a combination that is not built.  The
+ * autotuner installs its choices here. */
 int binar_get_default_params(uint32_t key_bytes, int has_payload, binar_params *out);
 int binar_set_default_params(uint32_t key_bytes, int has_payload, const binar_params *p);
+
+/* The parameters a call with `params` (may be NULL) would run with, every
+ * field filled in (finish_max clamped to the key width's largest LDS class);
+ * BINAR_EINVAL for a combination that is not built. */
+int binar_resolve_params(uint32_t key_bytes, int has_payload, const binar_params *params, binar_params *out);
 
 /* Launch timing for measurement.  While enabled (on = 1), every kernel the
  * library enqueues is bracketed by two HIP events recorded on the same
@@ -190,6 +200,10 @@ void binar_plan_destroy(binar_plan *plan);
 
 /* Static description of a status code. */
 const char *binar_strerror(int status);
+
+/* The HIP call behind the last BINAR_EDEVICE returned on this thread and
+ * HIP's message for it ("" if none); valid until the thread's next call. */
+const char *binar_last_error(void);
 
 #ifdef __cplusplus
 }

@@ -18,6 +18,7 @@ from .binar import (  # noqa: F401
     lib,
     profile_enable,
     profile_read,
+    resolve_params,
     set_default_params,
     sort,
     sort_segmented,

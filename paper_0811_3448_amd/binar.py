@@ -37,6 +37,11 @@ class _LaunchTime(ctypes.Structure):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libbinar.so is not built (%s); run python paper_0811_3448_amd/build.py" % LIB_PATH)
+    # torch brings its own HIP runtime; load it first so that the library's
+    # HIP runtime dependency resolves to the copy torch's tensors and streams
+    # live in.  Loaded the other way round, the library's runtime has been
+    # seen to find no device in a process where torch finds one.
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     vp, u32, u64, sz, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t, ctypes.c_int
     P = ctypes.POINTER(_Params)
@@ -49,6 +54,7 @@ def _load():
     L.binar_stats_read.argtypes = [vp, vp, ctypes.POINTER(_Stats)]
     L.binar_get_default_params.argtypes = [u32, i32, P]
     L.binar_set_default_params.argtypes = [u32, i32, P]
+    L.binar_resolve_params.argtypes = [u32, i32, P, P]
     L.binar_profile_enable.argtypes = [i32]
     L.binar_profile_read.argtypes = [ctypes.POINTER(_LaunchTime), u32, ctypes.POINTER(u32)]
     L.binar_plan_create.argtypes = [ctypes.POINTER(vp), u32, u64, u32, i32, P]
@@ -61,8 +67,10 @@ def _load():
     L.binar_plan_destroy.restype = None
     L.binar_strerror.argtypes = [i32]
     L.binar_strerror.restype = ctypes.c_char_p
+    L.binar_last_error.argtypes = []
+    L.binar_last_error.restype = ctypes.c_char_p
     for f in ("binar_sort", "binar_sort_async", "binar_sort_segmented", "binar_sort_ex",
-              "binar_stats_read", "binar_get_default_params", "binar_set_default_params",
+              "binar_stats_read", "binar_get_default_params", "binar_set_default_params", "binar_resolve_params",
               "binar_profile_enable", "binar_profile_read", "binar_plan_create", "binar_plan_sort",
               "binar_plan_stats", "binar_plan_graphs"):
         getattr(L, f).restype = i32
@@ -75,7 +83,8 @@ lib = _load()
 class BinarError(RuntimeError):
     def __init__(self, status: int):
         self.status = status
-        super().__init__("binar: %s (status %d)" % (strerror(status), status))
+        detail = lib.binar_last_error().decode() if status == BINAR_EDEVICE else ""
+        super().__init__("binar: %s (status %d)%s" % (strerror(status), status, "; " + detail if detail else ""))
 
 
 def strerror(status: int) -> str:
@@ -270,6 +279,14 @@ def default_params(key_bytes: int, has_payload: bool) -> Params:
     p = _Params()
     _check(lib.binar_get_default_params(key_bytes, 1 if has_payload else 0, ctypes.byref(p)))
     return Params(p.digit_bits, p.tile_keys, p.finish_max, p.offsets)
+
+
+def resolve_params(key_bytes: int, has_payload: bool, params: Params | None = None) -> Params:
+    """The parameters a call with `params` would run with, all fields set."""
+    p = _Params()
+    _check(lib.binar_resolve_params(key_bytes, 1 if has_payload else 0,
+                                    None if params is None else ctypes.byref(params.c()), ctypes.byref(p)))
+    return Params(p.digit_bits, p.tile_keys, p.finish_max, p.offsets, p.key_bits)
 
 
 def set_default_params(key_bytes: int, has_payload: bool, params: Params) -> None:

@@ -24,6 +24,20 @@ namespace {
 
 constexpr size_t ALIGN = 256;
 
+// Text of the last HIP failure seen on this thread (binar_last_error).
+thread_local char t_err[192];
+
+int hip_fail(const char *what, hipError_t e) {
+    std::snprintf(t_err, sizeof(t_err), "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+    return BINAR_EDEVICE;
+}
+
+#define BINAR_HIP_TRY(call)                                   \
+    do {                                                      \
+        const hipError_t e_ = (call);                         \
+        if (e_ != hipSuccess) return hip_fail(#call, e_);     \
+    } while (0)
+
 size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
 
 // LDS-finish classes: a block of FIN_BT threads, keys per thread of each
@@ -86,16 +100,13 @@ int kb_index(uint32_t kb) { return kb == 4 ? 0 : (kb == 8 ? 1 : 2); }
 
 bool valid_kb(uint32_t kb) { return kb == 4 || kb == 8 || kb == 16; }
 
-bool supported_k(uint32_t k) { return k == 1 || k == 4 || k == 8; }
+bool supported_k(uint32_t k) { return k == 1 || (k >= 4 && k <= 8); }
 
 bool supported_tile(uint32_t t) { return t == 2048 || t == 4096 || t == 8192; }
 
-int resolve(uint32_t kb, bool pay, const binar_params *p, Resolved *r) {
-    binar_params d;
-    {
-        std::lock_guard<std::mutex> lk(g_mu);
-        d = g_defaults[kb_index(kb)][pay ? 1 : 0];
-    }
+// Effective parameters: the nonzero fields of p over the defaults d, then
+// the built-in choices for what is still zero.
+int resolve_over(uint32_t kb, bool pay, binar_params d, const binar_params *p, Resolved *r) {
     if (p) {
         if (p->digit_bits) d.digit_bits = p->digit_bits;
         if (p->tile_keys) d.tile_keys = p->tile_keys;
@@ -109,6 +120,7 @@ int resolve(uint32_t kb, bool pay, const binar_params *p, Resolved *r) {
     if (!d.finish_max) d.finish_max = tmax;
     if (!supported_k(d.digit_bits) || !supported_tile(d.tile_keys) || d.offsets > 2) return BINAR_EINVAL;
     if (d.tile_keys == 8192 && (kb != 4 || d.digit_bits != 8)) return BINAR_EINVAL;
+    if (d.tile_keys == 2048 && d.digit_bits > 4 && d.digit_bits < 8) return BINAR_EINVAL;
     const uint32_t nbits = (p && p->key_bits) ? p->key_bits : 8u * kb;
     if (nbits > 8u * kb) return BINAR_EINVAL;
     r->nbits = nbits;
@@ -119,6 +131,15 @@ int resolve(uint32_t kb, bool pay, const binar_params *p, Resolved *r) {
     r->pay = pay;
     r->lookback = d.offsets == 2;
     return BINAR_OK;
+}
+
+int resolve(uint32_t kb, bool pay, const binar_params *p, Resolved *r) {
+    binar_params d;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        d = g_defaults[kb_index(kb)][pay ? 1 : 0];
+    }
+    return resolve_over(kb, pay, d, p, r);
 }
 
 Layout make_layout(const Resolved &r, uint64_t n) {
@@ -173,8 +194,8 @@ int pool_get(int dev, size_t bytes, void **out) {
     Pool &p = g_pools[dev];
     if (p.bytes < bytes) {
         if (p.ptr) {
-            if (hipDeviceSynchronize() != hipSuccess) return BINAR_EDEVICE;
-            if (hipFree(p.ptr) != hipSuccess) return BINAR_EDEVICE;
+            BINAR_HIP_TRY(hipDeviceSynchronize());
+            BINAR_HIP_TRY(hipFree(p.ptr));
             p.ptr = nullptr;
             p.bytes = 0;
         }
@@ -393,7 +414,8 @@ int enqueue(Work w, const Layout &L, const uint32_t *seg_off, uint32_t nseg, uin
                            dim3(grid_for(k_finish<KB, FIN_BT, I3, PAY>, L.max_fin[3], FIN_BT)), dim3(FIN_BT), 0, st,
                            w, 3);
     }
-    return hipGetLastError() == hipSuccess ? BINAR_OK : BINAR_EDEVICE;
+    BINAR_HIP_TRY(hipGetLastError());
+    return BINAR_OK;
 }
 
 template <int KB, bool PAY>
@@ -408,6 +430,9 @@ int dispatch_k(const Resolved &r, const Work &w, const Layout &L, const uint32_t
     }
     BINAR_CASE(8, 4096)
     BINAR_CASE(8, 2048)
+    BINAR_CASE(7, 4096)
+    BINAR_CASE(6, 4096)
+    BINAR_CASE(5, 4096)
     BINAR_CASE(4, 4096)
     BINAR_CASE(4, 2048)
     BINAR_CASE(1, 4096)
@@ -451,7 +476,7 @@ int run(void *keys, uint32_t kb, uint64_t n, uint32_t *payload, const uint32_t *
     if (rc) return rc;
     const Layout L = make_layout(r, n);
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return BINAR_EDEVICE;
+    BINAR_HIP_TRY(hipGetDevice(&dev));
     if (ws) {
         if (ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & (ALIGN - 1))) return BINAR_ENOMEM;
     } else {
@@ -459,6 +484,7 @@ int run(void *keys, uint32_t kb, uint64_t n, uint32_t *payload, const uint32_t *
         if (rc) return rc;
     }
     note_ws(dev, ws);
+    (void)hipGetLastError();  // a stale error of earlier, unrelated HIP calls is not ours
     const Work w = make_work(L, r, static_cast<char *>(ws), keys, payload, (uint32_t)n);
     return dispatch(r, w, L, seg_off, seg_off ? nseg : 1u, (uint32_t)n, st);
 }
@@ -524,9 +550,9 @@ int binar_plan_create(binar_plan **out, uint32_t key_bytes, uint64_t max_keys, u
     p->max_keys = max_keys < 2 ? 2 : max_keys;
     p->max_segments = max_segments;
     p->L = make_layout(p->r, p->max_keys);
-    if (hipGetDevice(&p->dev) != hipSuccess) {
+    if (const hipError_t e = hipGetDevice(&p->dev)) {
         delete p;
-        return BINAR_EDEVICE;
+        return hip_fail("hipGetDevice", e);
     }
     if (hipMalloc(&p->ws, p->L.total) != hipSuccess) {
         (void)hipGetLastError();
@@ -534,9 +560,9 @@ int binar_plan_create(binar_plan **out, uint32_t key_bytes, uint64_t max_keys, u
         plan_free(p);
         return BINAR_ENOMEM;
     }
-    if (hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess) {
+    if (const hipError_t e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking)) {
         plan_free(p);
-        return BINAR_EDEVICE;
+        return hip_fail("hipStreamCreateWithFlags", e);
     }
     *out = p;
     return BINAR_OK;
@@ -556,14 +582,16 @@ int binar_plan_sort(binar_plan *p, void *keys, uint32_t *payload, const uint32_t
     // segmented: the buffers hold the plan's capacity and the device checks
     // the offsets against it, so one graph serves every batch on them
     if (seg_offsets) n_total = p->max_keys;
+    (void)hipGetLastError();  // a stale error of earlier, unrelated HIP calls is not ours
     for (auto &g : p->graphs)
         if (g.keys == keys && g.pay == payload && g.off == seg_offsets && g.nseg == nseg && g.n == n_total) {
             note_ws(p->dev, p->ws);
-            return hipGraphLaunch(g.ge, st) == hipSuccess ? BINAR_OK : BINAR_EDEVICE;
+            BINAR_HIP_TRY(hipGraphLaunch(g.ge, st));
+            return BINAR_OK;
         }
     // capture the launch sequence once for these buffers
     Work w = make_work(p->L, p->r, static_cast<char *>(p->ws), keys, payload, (uint32_t)n_total);
-    if (hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return BINAR_EDEVICE;
+    BINAR_HIP_TRY(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
     t_capturing = true;
     int rc = dispatch(p->r, w, p->L, seg_offsets, nseg, (uint32_t)n_total, p->cap);
     t_capturing = false;
@@ -571,12 +599,12 @@ int binar_plan_sort(binar_plan *p, void *keys, uint32_t *payload, const uint32_t
     const hipError_t e = hipStreamEndCapture(p->cap, &g);
     if (rc || e != hipSuccess || !g) {
         if (g) (void)hipGraphDestroy(g);
-        return rc ? rc : BINAR_EDEVICE;
+        return rc ? rc : hip_fail("hipStreamEndCapture", e != hipSuccess ? e : hipErrorUnknown);
     }
     hipGraphExec_t ge = nullptr;
-    if (hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess) {
+    if (const hipError_t ei = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0)) {
         (void)hipGraphDestroy(g);
-        return BINAR_EDEVICE;
+        return hip_fail("hipGraphInstantiate", ei);
     }
     if (p->graphs.size() >= 16) {
         (void)hipGraphExecDestroy(p->graphs.front().ge);
@@ -585,7 +613,8 @@ int binar_plan_sort(binar_plan *p, void *keys, uint32_t *payload, const uint32_t
     }
     p->graphs.push_back(binar_plan::Graph{keys, payload, seg_offsets, nseg, n_total, g, ge});
     note_ws(p->dev, p->ws);
-    return hipGraphLaunch(ge, st) == hipSuccess ? BINAR_OK : BINAR_EDEVICE;
+    BINAR_HIP_TRY(hipGraphLaunch(ge, st));
+    return BINAR_OK;
 }
 
 int binar_plan_stats(binar_plan *p, void *stream, binar_stats *out) {
@@ -650,12 +679,12 @@ int binar_stats_read(const void *workspace, void *stream, binar_stats *out) {
     if (!out) return BINAR_EINVAL;
     std::memset(out, 0, sizeof(*out));
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return BINAR_EDEVICE;
+    BINAR_HIP_TRY(hipGetDevice(&dev));
     const void *ws = workspace ? workspace : last_ws(dev);
     if (!ws) return BINAR_EINVAL;
-    if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess) return BINAR_EDEVICE;
+    BINAR_HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
     Ctl c;
-    if (hipMemcpy(&c, ws, sizeof(Ctl), hipMemcpyDeviceToHost) != hipSuccess) return BINAR_EDEVICE;
+    BINAR_HIP_TRY(hipMemcpy(&c, ws, sizeof(Ctl), hipMemcpyDeviceToHost));
     for (int j = 0; j < MAX_PASSES; ++j) {
         out->moved[j] = c.moved[j];
         out->hist_keys[j] = c.hist_keys[j];
@@ -673,25 +702,32 @@ int binar_stats_read(const void *workspace, void *stream, binar_stats *out) {
     return BINAR_OK;
 }
 
-int binar_get_default_params(uint32_t key_bytes, int has_payload, binar_params *out) {
+int binar_resolve_params(uint32_t key_bytes, int has_payload, const binar_params *params, binar_params *out) {
     if (!valid_kb(key_bytes) || !out) return BINAR_EINVAL;
     Resolved r;
-    int rc = resolve(key_bytes, has_payload != 0, nullptr, &r);
+    int rc = resolve(key_bytes, has_payload != 0, params, &r);
     if (rc) return rc;
+    std::memset(out, 0, sizeof(*out));
     out->digit_bits = r.k;
     out->tile_keys = r.tile;
     out->finish_max = r.T;
     out->offsets = r.lookback ? 2u : 1u;
+    out->key_bits = r.nbits;
     return BINAR_OK;
+}
+
+int binar_get_default_params(uint32_t key_bytes, int has_payload, binar_params *out) {
+    return binar_resolve_params(key_bytes, has_payload, nullptr, out);
 }
 
 int binar_set_default_params(uint32_t key_bytes, int has_payload, const binar_params *p) {
     if (!valid_kb(key_bytes) || !p) return BINAR_EINVAL;
-    if (p->digit_bits && !supported_k(p->digit_bits)) return BINAR_EINVAL;
-    if (p->tile_keys && !supported_tile(p->tile_keys)) return BINAR_EINVAL;
-    if (p->offsets > 2) return BINAR_EINVAL;
+    binar_params d = *p;
+    d.key_bits = 0;  // the defaults always sort whole keys
+    Resolved r;
+    if (int rc = resolve_over(key_bytes, has_payload != 0, d, nullptr, &r)) return rc;
     std::lock_guard<std::mutex> lk(g_mu);
-    g_defaults[kb_index(key_bytes)][has_payload ? 1 : 0] = *p;
+    g_defaults[kb_index(key_bytes)][has_payload ? 1 : 0] = d;
     return BINAR_OK;
 }
 
@@ -716,8 +752,9 @@ int binar_profile_read(binar_launch_time *out, uint32_t cap, uint32_t *count) {
     for (auto &r : g_prof.recs) {
         if (k < cap) {
             float ms = 0.f;
-            if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess)
-                rc = BINAR_EDEVICE;
+            hipError_t e = hipEventSynchronize(r.b);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+            if (e != hipSuccess) rc = hip_fail("binar_profile_read", e);
             std::memcpy(out[k].name, r.name, sizeof(out[k].name));
             out[k].pass = r.pass;
             out[k].ms = ms;
@@ -730,6 +767,8 @@ int binar_profile_read(binar_launch_time *out, uint32_t cap, uint32_t *count) {
     *count = k;
     return rc;
 }
+
+const char *binar_last_error(void) { return binar::t_err; }
 
 const char *binar_strerror(int status) {
     switch (status) {

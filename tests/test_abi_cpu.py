@@ -59,6 +59,14 @@ def test_bad_tuning_knobs(lib):
                              None, None, 0) == -1
     with pytest.raises(binar.BinarError):
         binar.set_default_params(4, True, binar.Params(tile_keys=1000))
+    # built digit/tile pairs: every digit width at 4096; 2048 only for 1, 4, 8
+    for k in (2, 3, 9):
+        assert binar.workspace_bytes(4, 1000, True, params=binar.Params(digit_bits=k)) == 0
+    for k in (1, 4, 5, 6, 7, 8):
+        assert binar.workspace_bytes(8, 1000, True, params=binar.Params(digit_bits=k, tile_keys=4096)) > 0
+    for k in (5, 6, 7):
+        assert binar.workspace_bytes(4, 1000, True, params=binar.Params(digit_bits=k, tile_keys=2048)) == 0
+        assert binar.workspace_bytes(4, 1000, True, params=binar.Params(digit_bits=k, tile_keys=8192)) == 0
 
 
 def test_workspace_bytes(lib):

@@ -72,6 +72,20 @@ def test_u32_global_passes(k, tile, T, offsets):
     compare(workloads.u32_dup(n, 22 + k, 256), params=P(k, tile, T, offsets))
 
 
+@pytest.mark.parametrize("k", [5, 6, 7])
+@pytest.mark.parametrize("kb", [4, 8, 16])
+def test_odd_digit_widths(k, kb):
+    """Digits of 5, 6 or 7 bits straddle byte (and, for 16-byte keys, word)
+    boundaries, and the last pass takes fewer than k bits."""
+    n = 90_001
+    keys = {4: lambda: workloads.u32_uniform(n, 60 + k), 8: lambda: workloads.u64_zipf(n, 61 + k, 1 << 12, 1.1),
+            16: lambda: workloads.str16(n, 62 + k, 7)}[kb]()
+    for T, offsets in ((0, 1), (150, 1), (150, 2)):
+        compare(keys, params=P(k, 4096, T, offsets))
+    if kb == 4:
+        compare(workloads.u32_and4(n, 63 + k), params=P(k, 4096, 1, 1))
+
+
 @pytest.mark.parametrize("offsets", [1, 2])
 def test_u32_many_chunks(offsets):
     """Several million keys: every chunk holds many tiles, pieces of many

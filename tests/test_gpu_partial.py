@@ -42,7 +42,7 @@ def test_u32_after_each_pass(offsets, dist, T):
         check_partial(keys, nbits, finish_max=T, offsets=offsets)
 
 
-@pytest.mark.parametrize("k", [1, 4])
+@pytest.mark.parametrize("k", [1, 4, 5, 7])
 def test_u32_binary_steps(k):
     """k = 1 is the paper's one-bit partition, made stable."""
     n = 50_001
