@@ -65,6 +65,25 @@ def cpu_baseline(keys_np, log2_sample: int):
                       "partition in C on one host core, %.1f s" % (log2_sample, dt)}
 
 
+def choose_params(binar, args, kb, has_pay, n, batched):
+    """Command-line knobs if any is given, else the autotune cache's entry
+    for this case (tuned on the device), else the library defaults."""
+    if args.digit_bits or args.tile_keys or args.finish_max or args.offsets:
+        return binar.Params(args.digit_bits, args.tile_keys, args.finish_max, args.offsets), "command line"
+    if not args.untuned:
+        from paper_0811_3448_amd import tune
+        p = tune.TuneCache(arch=tune.device_arch()).lookup(kb, has_pay, n, batched, max_distance=1)
+        if p is not None:
+            return p, "autotune cache"
+    return binar.Params(), "library defaults"
+
+
+def describe_params(binar, kb, has_pay, params, source):
+    r = binar.resolve_params(kb, has_pay, params)
+    return {"digit_bits": r.digit_bits, "tile_keys": r.tile_keys, "finish_max": r.finish_max,
+            "offsets": "decoupled look-back" if r.offsets == 2 else "chunk prefixes", "params_from": source}
+
+
 def bench_batched(args) -> int:
     """Batched workload: 100,000 lognormal segments of u32 keys (+ global
     index payload), about 2^27 keys.  One HIP-graph replay of the segmented
@@ -82,7 +101,8 @@ def bench_batched(args) -> int:
     pay0 = torch.arange(n, dtype=torch.int32, device=dev)
     kbuf, pbuf = pristine.clone(), pay0.clone()
     off = torch.from_numpy(off_np.astype(np.uint32).view(np.int32)).to(dev)
-    plan = binar.Plan(4, n, S, True)
+    params, source = choose_params(binar, args, 4, True, n, batched=True)
+    plan = binar.Plan(4, n, S, True, params)
     stream = torch.cuda.current_stream()
 
     def restore():
@@ -107,8 +127,25 @@ def bench_batched(args) -> int:
         raise RuntimeError("batched sort status %d" % st["status"])
     graph_ms = float(np.median(times))
 
+    # per-kernel breakdown: one eager call of the same sort, each launch
+    # bracketed by events (outside the timed replays)
+    restore()
+    ws_b = binar.Workspace(binar.workspace_bytes(4, n, True, S, params))
+    torch.cuda.synchronize()
+    binar.profile_enable(True)
+    binar.profile_read()
+    binar.sort_segmented(kbuf, off, pbuf, workspace=ws_b, params=params)
+    torch.cuda.synchronize()
+    prof = binar.profile_read()
+    binar.profile_enable(False)
+    kernels = {}
+    for nm, _p, ms in prof:
+        kernels[nm] = round(kernels.get(nm, 0.0) + ms, 4)
+    st_e = binar.stats(ws_b)
+    del ws_b
+
     # one library call per array, all enqueued on the stream with one workspace
-    ws = binar.Workspace(binar.workspace_bytes(4, int(np.diff(off_np).max()), True))
+    ws = binar.Workspace(binar.workspace_bytes(4, int(np.diff(off_np).max()), True, 1, params))
     offs = off_np.astype(np.int64).tolist()
     restore()
     torch.cuda.synchronize()
@@ -118,7 +155,7 @@ def bench_batched(args) -> int:
     for s in range(S):
         a, b = offs[s], offs[s + 1]
         if b - a > 1:
-            binar.sort(kbuf[a:b], pbuf[a:b], workspace=ws)
+            binar.sort(kbuf[a:b], pbuf[a:b], workspace=ws, params=params)
     e1.record(stream)
     torch.cuda.synchronize()
     per_array_ms = e0.elapsed_time(e1)
@@ -130,11 +167,14 @@ def bench_batched(args) -> int:
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": "batched_u32_100k: %d lognormal segments (median 1024, sigma 0.7356), %d u32 keys "
-                               "+ u32 index payload" % (S, n), "segments": S, "n": n},
+                               "+ u32 index payload" % (S, n), "segments": S, "n": n,
+                   **describe_params(binar, 4, True, params, source)},
         "per_array_calls": {"ms": round(per_array_ms, 2), "gkeys_s": round(n / (per_array_ms * 1e-3) / 1e9, 3),
                             "host_wall_s": round(per_array_wall, 2)},
         "speedup_vs_per_array": round(per_array_ms / graph_ms, 2),
         "finish_segments": st["finish_segments"], "passes": st["passes"],
+        "eager_kernels_ms": kernels,
+        "finish_class_segments": st_e["finish_class_segments"], "finish_class_keys": st_e["finish_class_keys"],
     }
     print(json.dumps(result), flush=True)
     return 0
@@ -152,6 +192,7 @@ def main() -> int:
     ap.add_argument("--tile-keys", type=int, default=0)
     ap.add_argument("--finish-max", type=int, default=0)
     ap.add_argument("--offsets", type=int, default=0, help="1 = chunk prefixes, 2 = decoupled look-back")
+    ap.add_argument("--untuned", action="store_true", help="ignore the autotune cache: library defaults")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -187,7 +228,7 @@ def main() -> int:
     pay0 = torch.arange(n, dtype=torch.int32, device=dev) if has_pay else None
     K, W = args.steps, args.warmup
     bufs = [(pristine.clone(), None if pay0 is None else pay0.clone()) for _ in range(K + W)]
-    params = binar.Params(args.digit_bits, args.tile_keys, args.finish_max, args.offsets)
+    params, source = choose_params(binar, args, kb, has_pay, n, batched=False)
     ws = binar.Workspace(binar.workspace_bytes(kb, n, has_pay, 1, params), device=dev)
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
@@ -267,11 +308,7 @@ def main() -> int:
         "dtype": "u32" if kb == 4 else ("u64" if kb == 8 else "u8x16"),
         "data": "synthetic",
         "config": {"workload": "%s: %s" % (name, desc), "n": n, "key_bytes": kb, "payload_bytes": pb,
-                   "digit_bits": binar.default_params(kb, has_pay).digit_bits if not args.digit_bits
-                   else args.digit_bits,
-                   "tile_keys": args.tile_keys or binar.default_params(kb, has_pay).tile_keys,
-                   "finish_max": args.finish_max or binar.default_params(kb, has_pay).finish_max,
-                   "offsets": "decoupled look-back" if args.offsets == 2 else "chunk prefixes",
+                   **describe_params(binar, kb, has_pay, params, source),
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

@@ -565,6 +565,9 @@ __global__ __launch_bounds__(THREADS) void k_plan(Work w, int L, int pass) {
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicMax(&ctl->passes, (unsigned)(pass + 1));
     const int ps = pass < MAX_PASSES ? pass : MAX_PASSES - 1;
     const int d = threadIdx.x;
+    // statistics: summed per block, one atomic each at the end (per-segment
+    // atomics on one address serialise the whole grid)
+    unsigned long long st_hist = 0ull, st_moved = 0ull;
 
     for (uint32_t s = blockIdx.x; s < nslots; s += gridDim.x) {
         const SegEntry seg = w.list[L][s];
@@ -575,7 +578,7 @@ __global__ __launch_bounds__(THREADS) void k_plan(Work w, int L, int pass) {
         const int nz = __syncthreads_count(c != 0u);
         const unsigned long long *ao = w.andor[L] + (size_t)s * 4;
         const Canon diff{ao[0] ^ ao[2], ao[1] ^ ao[3]};
-        if (d == 0) atomicAdd(&ctl->hist_keys[ps], (unsigned long long)seg.len);
+        st_hist += seg.len;
 
         if (nz == 1) {
             // pass-through: every key has the same digit here
@@ -585,7 +588,7 @@ __global__ __launch_bounds__(THREADS) void k_plan(Work w, int L, int pass) {
                 // all keys equal: done; if they sit in B the scatter copies them to A
                 if (parity == 1u) {
                     if (c != 0u) w.bases[L][(size_t)s * R + d] = seg.begin;
-                    if (d == 0) atomicAdd(&ctl->moved[ps], (unsigned long long)seg.len);
+                    st_moved += seg.len;
                 } else if (d == 0) {
                     w.list[L][s].info = seg.info | (SEG_SKIP << 16);
                 }
@@ -612,7 +615,7 @@ __global__ __launch_bounds__(THREADS) void k_plan(Work w, int L, int pass) {
             w.bases[L][(size_t)s * R + d] = seg.begin + excl;
             if (!done) cat = (c <= w.finish_max) ? fin_class(w, c) : NCLASS;
         }
-        if (d == 0) atomicAdd(&ctl->moved[ps], (unsigned long long)seg.len);
+        st_moved += seg.len;
         if (parity == 0u) {
             // finished children land in B: one copy-back range per run of
             // adjacent finished children (empty digits do not break a run)
@@ -642,6 +645,10 @@ __global__ __launch_bounds__(THREADS) void k_plan(Work w, int L, int pass) {
         }
         block_append<R>(w, L ^ 1, cat, seg.begin + excl, c, cb, child_parity, s_tmp, s_base);
     }
+    if (d == 0) {
+        if (st_hist) atomicAdd(&ctl->hist_keys[ps], st_hist);
+        if (st_moved) atomicAdd(&ctl->moved[ps], st_moved);
+    }
 }
 
 // -------------------------------------------------------------- k_copyback
@@ -652,19 +659,21 @@ __global__ __launch_bounds__(THREADS) void k_copyback(Work w) {
     Ctl *ctl = w.ctl;
     if (ctl->error | ctl->overflow) return;
     const uint32_t n = min(ctl->cpy_ctr, w.max_cpy);
+    unsigned long long st_keys = 0ull;
     for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
         const CopyEntry e = w.cpy[i];
         if ((size_t)e.begin + e.len > w.n_total) {
             if (threadIdx.x == 0) atomicOr(&ctl->error, ERR_INTERNAL);
             continue;
         }
-        if (threadIdx.x == 0) atomicAdd(&ctl->cpy_keys, (unsigned long long)e.len);
+        st_keys += e.len;
         for (uint32_t k = threadIdx.x; k < e.len; k += THREADS) {
             const size_t g = (size_t)e.begin + k;
             KT::store(w.keys[0], g, KT::load(w.keys[1], g));
             if (PAY) w.pay[0][g] = w.pay[1][g];
         }
     }
+    if (threadIdx.x == 0 && st_keys) atomicAdd(&ctl->cpy_keys, st_keys);
 }
 
 // ---------------------------------------------------------------- k_scatter
@@ -1050,6 +1059,7 @@ __global__ __launch_bounds__(BT) void k_finish(Work w, int cls) {
     for (int i = threadIdx.x; i < NW * R; i += BT) (&S.tbl[0][0][0])[i] = 0ull;
     __syncthreads();
 
+    unsigned long long st_keys = 0ull, st_segs = 0ull;  // flushed once per block
     for (uint32_t f = blockIdx.x; f < nfin; f += gridDim.x) {
         const FinEntry fe = uni(w.fin[cls][f]);
         const uint32_t len = fe.info & 0xFFFFu;
@@ -1059,10 +1069,8 @@ __global__ __launch_bounds__(BT) void k_finish(Work w, int cls) {
             if (threadIdx.x == 0) atomicOr(&ctl->error, ERR_INTERNAL);
             continue;
         }
-        if (threadIdx.x == 0) {
-            atomicAdd(&ctl->fin_keys[cls], (unsigned long long)len);
-            atomicAdd(&ctl->fin_segs[cls], 1ull);
-        }
+        st_keys += len;
+        ++st_segs;
         const char *src = static_cast<const char *>(w.keys[parity]) + (size_t)fe.begin * KB;
         const uint32_t *psrc = PAY ? w.pay[parity] + fe.begin : nullptr;
 
@@ -1167,6 +1175,10 @@ __global__ __launch_bounds__(BT) void k_finish(Work w, int cls) {
             if (PAY) pdst[p] = S.pay[p];
         }
         __syncthreads();
+    }
+    if (threadIdx.x == 0 && st_segs) {
+        atomicAdd(&ctl->fin_keys[cls], st_keys);
+        atomicAdd(&ctl->fin_segs[cls], st_segs);
     }
 }
 
