@@ -180,6 +180,87 @@ def bench_batched(args) -> int:
     return 0
 
 
+def bench_serve(args) -> int:
+    """Serving workload: Poisson arrivals of sort requests, sizes log-uniform
+    in [2^8, 2^24] keys, key widths u32 / u64 / 16-byte = 50 / 30 / 20 %,
+    each answered with sorted keys and permutation.  The same arrival trace
+    runs twice: continuous batching (segmented graph replays on two streams
+    per width) and one request per launch in arrival order."""
+    import numpy as np
+    import torch
+    from paper_0811_3448_amd import tune
+    from paper_0811_3448_amd.serve import Server
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    rng = np.random.default_rng(0x5E7E)
+    R, rate = args.serve_requests, args.serve_rate
+    gaps = rng.exponential(1.0 / rate, R)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    sizes = np.floor(2.0 ** rng.uniform(8, 24, R)).astype(np.int64)
+    widths = rng.choice([4, 8, 16], size=R, p=[0.5, 0.3, 0.2])
+    pool_n = 1 << 25
+    pools = {4: tune.synth_keys(4, pool_n, 11, dev), 8: tune.synth_keys(8, pool_n, 12, dev),
+             16: tune.synth_keys(16, pool_n, 13, dev)}
+    starts = (rng.random(R) * (pool_n - sizes)).astype(np.int64)
+    reqs = [pools[int(w)][int(a):int(a) + int(n)] for w, a, n in zip(widths, starts, sizes)]
+    torch.cuda.synchronize()
+    total_keys = int(sizes.sum())
+    cache = tune.TuneCache(arch=tune.device_arch())
+
+    def lookup(kb, cap):
+        return cache.lookup(kb, True, cap, True, max_distance=4)
+
+    def run(batching):
+        srv = Server(budget_bytes=args.serve_budget_gib << 30, streams=2, max_batch_keys=1 << 25,
+                     max_batch_requests=1024, batching=batching, params_lookup=lookup)
+        # warm the lanes (first batch of each lane captures its graph)
+        warm = [srv.submit(pools[w][:4096]) for w in (4, 8, 16) for _ in range(2)]
+        for f in warm:
+            f.result()
+        srv.records.clear()
+        done = []
+        t0 = time.perf_counter()
+        for i in range(R):
+            delay = t0 + arrivals[i] - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            f = srv.submit(reqs[i])
+            f.add_done_callback(lambda f: done.append(1))
+            if i % 500 == 0:
+                print("bench: serve %s submitted %d/%d" % ("batched" if batching else "fifo", i, R),
+                      file=sys.stderr, flush=True)
+        srv.close()
+        rep = srv.report()
+        rep["offered_keys_s"] = total_keys / max(arrivals[-1], 1e-9)
+        return rep
+
+    batched = run(True)
+    fifo = run(False)
+
+    def fmt(rep):
+        return {"p50_ms": round(rep["p50_s"] * 1e3, 3), "p99_ms": round(rep["p99_s"] * 1e3, 3),
+                "max_ms": round(rep["max_s"] * 1e3, 3),
+                "throughput_gkeys_s": round(rep["throughput_keys_s"] / 1e9, 3),
+                "batches": rep["batches"], "requests": rep["requests"],
+                "peak_admitted_gib": round(rep["peak_admitted_bytes"] / 2 ** 30, 3),
+                "max_waiting": rep["max_waiting"]}
+    result = {
+        "metric": "serving throughput (Gkeys/s) with p50/p99 latency, Poisson sort requests",
+        "value": round(batched["throughput_keys_s"] / 1e9, 3), "unit": "Gkeys/s", "n_gpus": 1,
+        "steps": 1, "warmup": 1, "ms_per_step": round(total_keys / batched["throughput_keys_s"] * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32/u64/u8x16",
+        "data": "synthetic",
+        "config": {"workload": "serve_c5: %d requests, Poisson %.0f req/s, sizes log-uniform 2^8..2^24, "
+                               "u32/u64/16 B = 50/30/20 %%, u32 index payload" % (R, rate),
+                   "requests": R, "keys": total_keys, "offered_gkeys_s": round(batched["offered_keys_s"] / 1e9, 3),
+                   "budget_gib": args.serve_budget_gib},
+        "batched": fmt(batched), "one_request_per_launch": fmt(fifo),
+    }
+    print(json.dumps(result), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -193,6 +274,9 @@ def main() -> int:
     ap.add_argument("--finish-max", type=int, default=0)
     ap.add_argument("--offsets", type=int, default=0, help="1 = chunk prefixes, 2 = decoupled look-back")
     ap.add_argument("--untuned", action="store_true", help="ignore the autotune cache: library defaults")
+    ap.add_argument("--serve-requests", type=int, default=3000)
+    ap.add_argument("--serve-rate", type=float, default=4000.0, help="Poisson arrival rate, requests/s")
+    ap.add_argument("--serve-budget-gib", type=int, default=24)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -213,6 +297,8 @@ def main() -> int:
 
     if args.workload == "batched_u32_100k":
         return bench_batched(args)
+    if args.workload == "serve_c5":
+        return bench_serve(args)
 
     name = args.workload
     kb, n, has_pay, desc = workloads.SINGLE[name]

@@ -1,0 +1,394 @@
+"""Serving loop for sort requests on one GPU.
+
+Requests (device tensors of keys: 4-byte, 8-byte or 16-byte, see
+``key_bytes_of``) arrive over time through ``Server.submit`` and are answered
+through a ``concurrent.futures.Future`` with the sorted keys and the stable
+sorting permutation (int32 holding uint32 indices into the request).
+
+* Admission: a request costs ``2 * (key_bytes + 4) * n + META_BYTES`` bytes
+  of the HBM budget (its keys and permutation, and their share of the sort's
+  ping-pong scratch).  It is admitted in arrival order while the bytes of
+  admitted, unfinished requests stay within the budget; otherwise it waits.
+  A request that could never fit is refused at submit with BINAR_ENOMEM.
+* Batching: admitted requests of one key width are packed, in admission
+  order, into the resident buffers of a lane (one per stream and width) and
+  sorted as the segments of one segmented sort: one replay of the lane's
+  captured HIP graph.  Lanes run on separate streams, so batches overlap.
+  A lane takes up to ``max_batch_keys`` keys and ``max_batch_requests``
+  requests; whatever has been admitted when a lane frees up goes in.
+* Completion: when a lane's batch has finished, each request's results are
+  already in tensors of its own; its budget is released and its Future set.
+* Cancelling a Future before its batch starts frees its budget.
+
+One scheduler thread does admission, packing, launches and completion; the
+device work lives in a backend object (``DeviceBackend``), so the policy can
+be exercised with a host-only backend.
+"""
+from __future__ import annotations
+
+import threading
+import time
+from collections import deque
+from concurrent.futures import Future
+from dataclasses import dataclass
+
+from .binar import BINAR_ENOMEM, BinarError, key_bytes_of
+
+META_BYTES = 256
+WIDTHS = (4, 8, 16)
+
+
+def request_cost(key_bytes: int, n: int) -> int:
+    return 2 * (key_bytes + 4) * n + META_BYTES
+
+
+@dataclass
+class SortResult:
+    keys: object          # sorted keys, same shape and dtype as the request
+    perm: object          # int32 tensor: perm[i] = input index of keys[i]
+    submitted: float
+    admitted: float
+    launched: float
+    done: float
+    batch_requests: int
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.submitted
+
+
+@dataclass
+class _Req:
+    id: int
+    keys: object
+    kb: int
+    n: int
+    cost: int
+    future: Future
+    submitted: float
+    ready_event: object = None
+    admitted: float = 0.0
+    launched: float = 0.0
+
+
+class Admission:
+    """HBM-budget accounting with a FIFO wait queue (no device work)."""
+
+    def __init__(self, budget: int):
+        if budget <= 0:
+            raise ValueError("budget must be positive")
+        self.budget = int(budget)
+        self.in_use = 0
+        self.peak = 0
+        self.waiting: deque = deque()
+
+    def offer(self, req: _Req) -> None:
+        if req.cost > self.budget:
+            raise BinarError(BINAR_ENOMEM)
+        self.waiting.append(req)
+
+    def admit(self, now: float) -> list:
+        """Admit from the head of the queue while the budget allows; requests
+        cancelled while waiting are dropped without being charged."""
+        out = []
+        while self.waiting:
+            r = self.waiting[0]
+            if r.future.cancelled():
+                self.waiting.popleft()
+                continue
+            if self.in_use + r.cost > self.budget:
+                break
+            self.waiting.popleft()
+            self.in_use += r.cost
+            self.peak = max(self.peak, self.in_use)
+            r.admitted = now
+            out.append(r)
+        return out
+
+    def release(self, cost: int) -> None:
+        self.in_use -= cost
+        assert self.in_use >= 0
+
+
+class Server:
+    """Continuous-batching sort server; see the module docstring."""
+
+    def __init__(self, budget_bytes: int = 8 << 30, backend=None, streams: int = 2,
+                 max_batch_keys: int = 1 << 25, max_batch_requests: int = 1024, batching: bool = True,
+                 params_lookup=None, check_status: bool = False, clock=time.perf_counter):
+        self.max_batch_keys = int(max_batch_keys)
+        self.max_batch_requests = int(max_batch_requests) if batching else 1
+        self.clock = clock
+        self.admission = Admission(budget_bytes)
+        self.backend = backend if backend is not None else DeviceBackend(
+            streams, self.max_batch_keys, self.max_batch_requests, params_lookup, check_status=check_status)
+        self._cv = threading.Condition()
+        self._ready = {kb: deque() for kb in WIDTHS}
+        self._inflight: list = []
+        self._next_id = 0
+        self._running = True
+        self._error = None
+        self.records: list = []            # (n, submitted, admitted, launched, done, batch size) per request
+        self.batches = 0
+        self.max_waiting = 0
+        self._thread = threading.Thread(target=self._loop, name="binar-serve", daemon=True)
+        self._thread.start()
+
+    # ------------------------------------------------------------ client side
+    def submit(self, keys) -> Future:
+        """Queue one request.  `keys` is not modified; the caller must not
+        modify it either until the Future is done."""
+        kb = key_bytes_of(keys)
+        n = int(keys.shape[0])
+        if n > self.max_batch_keys:
+            raise BinarError(BINAR_ENOMEM)
+        fut: Future = Future()
+        with self._cv:
+            if not self._running:
+                raise RuntimeError("server is closed")
+            if self._error is not None:
+                raise RuntimeError("server failed") from self._error
+            req = _Req(self._next_id, keys, kb, n, request_cost(kb, n), fut, self.clock())
+            req.ready_event = self.backend.mark_ready(keys)
+            self.admission.offer(req)      # raises BINAR_ENOMEM for a request that can never fit
+            self._next_id += 1
+            self.max_waiting = max(self.max_waiting, len(self.admission.waiting))
+            self._cv.notify()
+        return fut
+
+    def close(self, wait: bool = True) -> None:
+        with self._cv:
+            self._running = False
+            self._cv.notify()
+        if wait:
+            self._thread.join()
+        if self._error is not None:
+            raise RuntimeError("server failed") from self._error
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def report(self) -> dict:
+        """Latency percentiles (seconds), throughput and counters over the
+        requests finished so far."""
+        recs = list(self.records)
+        lat = sorted(r[4] - r[1] for r in recs)
+        keys = sum(r[0] for r in recs)
+        span = (max(r[4] for r in recs) - min(r[1] for r in recs)) if recs else 0.0
+
+        def pct(p):
+            if not lat:
+                return None
+            return lat[min(len(lat) - 1, int(round(p / 100.0 * (len(lat) - 1))))]
+        return {"requests": len(lat), "keys": keys, "batches": self.batches,
+                "p50_s": pct(50), "p99_s": pct(99), "max_s": lat[-1] if lat else None,
+                "throughput_keys_s": keys / span if span > 0 else None,
+                "peak_admitted_bytes": self.admission.peak, "max_waiting": self.max_waiting}
+
+    # ------------------------------------------------------------- scheduler
+    def _loop(self):
+        try:
+            self.backend.thread_init()
+            while True:
+                progressed = False
+                with self._cv:
+                    now = self.clock()
+                    for r in self.admission.admit(now):
+                        self._ready[r.kb].append(r)
+                        progressed = True
+                    self._drop_cancelled()
+                    batches = self._form_batches()
+                    idle = (not self._running and not self.admission.waiting and not self._inflight
+                            and not any(self._ready.values()) and not batches)
+                if idle:
+                    return
+                for i, (lane, reqs) in enumerate(batches):
+                    t = self.clock()
+                    for r in reqs:
+                        r.launched = t
+                    try:
+                        h = self.backend.launch(lane, reqs)
+                    except BaseException:
+                        # these requests are in no queue any more: fail them here
+                        self._inflight += [(None, ln, rq) for ln, rq in batches[i:]]
+                        raise
+                    self._inflight.append((h, lane, reqs))
+                    self.batches += 1
+                    progressed = True
+                still = []
+                for h, lane, reqs in self._inflight:
+                    if self.backend.poll(h):
+                        self._complete(h, lane, reqs)
+                        progressed = True
+                    else:
+                        still.append((h, lane, reqs))
+                self._inflight = still
+                if not progressed:
+                    with self._cv:
+                        if self._running or self.admission.waiting or any(self._ready.values()):
+                            self._cv.wait(timeout=0.0002 if self._inflight else 0.01)
+        except BaseException as e:  # fail every pending request rather than hang the callers
+            self._error = e
+            with self._cv:
+                pending = list(self.admission.waiting) + [r for q in self._ready.values() for r in q]
+                pending += [r for _, _, reqs in self._inflight for r in reqs]
+                self.admission.waiting.clear()
+                for q in self._ready.values():
+                    q.clear()
+            for r in pending:
+                if not r.future.done():
+                    r.future.set_exception(e)
+
+    def _drop_cancelled(self):
+        for kb, q in self._ready.items():
+            if any(r.future.cancelled() for r in q):
+                keep = deque()
+                for r in q:
+                    if r.future.cancelled():
+                        self.admission.release(r.cost)
+                    else:
+                        keep.append(r)
+                self._ready[kb] = keep
+
+    def _form_batches(self) -> list:
+        out = []
+        for kb, q in self._ready.items():
+            while q:
+                lane = self.backend.free_lane(kb)
+                if lane is None:
+                    break
+                reqs, keys = [], 0
+                while q and len(reqs) < self.max_batch_requests and keys + q[0].n <= self.max_batch_keys:
+                    r = q.popleft()
+                    if not r.future.set_running_or_notify_cancel():
+                        self.admission.release(r.cost)
+                        continue
+                    reqs.append(r)
+                    keys += r.n
+                if not reqs:
+                    self.backend.release_lane(lane)
+                    continue
+                out.append((lane, reqs))
+        return out
+
+    def _complete(self, handle, lane, reqs):
+        outs = self.backend.collect(handle)
+        t = self.clock()
+        with self._cv:
+            for r in reqs:
+                self.admission.release(r.cost)
+            self._cv.notify()
+        self.backend.release_lane(lane)
+        for r, (k, p) in zip(reqs, outs):
+            self.records.append((r.n, r.submitted, r.admitted, r.launched, t, len(reqs)))
+            r.future.set_result(SortResult(k, p, r.submitted, r.admitted, r.launched, t, len(reqs)))
+
+
+class _Lane:
+    """Resident buffers of one stream and key width: keys, permutation,
+    segment table (device and pinned host copy), a plan whose graph is
+    captured on the first batch and replayed for every later one."""
+
+    def __init__(self, kb: int, cap: int, max_segments: int, device, params):
+        import torch
+        from .binar import Plan
+        self.kb, self.cap, self.max_segments = kb, cap, max_segments
+        self.stream = torch.cuda.Stream(device=device)
+        if kb == 16:
+            self.keys = torch.empty((cap, 16), dtype=torch.uint8, device=device)
+        else:
+            self.keys = torch.empty(cap, dtype=torch.int32 if kb == 4 else torch.int64, device=device)
+        self.pay = torch.empty(cap, dtype=torch.int32, device=device)
+        self.iota = torch.arange(cap, dtype=torch.int32, device=device)
+        self.off_dev = torch.zeros(max_segments + 1, dtype=torch.int32, device=device)
+        self.off_host = torch.zeros(max_segments + 1, dtype=torch.int32, pin_memory=True)
+        self.plan = Plan(kb, cap, max_segments, True, params)
+        self.done = torch.cuda.Event()
+        self.busy = False
+
+
+class DeviceBackend:
+    """Runs batches on the GPU: lanes are created on first use, up to
+    `streams` per key width."""
+
+    def __init__(self, streams: int, cap: int, max_segments: int, params_lookup=None, device=None,
+                 check_status: bool = False):
+        import torch
+        self.torch = torch
+        self.check_status = check_status
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self.streams, self.cap, self.max_segments = streams, cap, max_segments
+        self.params_lookup = params_lookup
+        self.lanes = {kb: [] for kb in WIDTHS}
+
+    def thread_init(self):
+        self.torch.cuda.set_device(self.device)
+
+    def mark_ready(self, keys):
+        """Event on the submitting thread's current stream: the lane waits
+        for it before reading the request's keys."""
+        if not keys.is_cuda or keys.device != self.device or not keys.is_contiguous():
+            raise ValueError("keys must be a contiguous tensor on %s" % self.device)
+        ev = self.torch.cuda.Event()
+        ev.record()
+        return ev
+
+    def free_lane(self, kb):
+        for lane in self.lanes[kb]:
+            if not lane.busy:
+                lane.busy = True
+                return lane
+        if len(self.lanes[kb]) < self.streams:
+            params = None if self.params_lookup is None else self.params_lookup(kb, self.cap)
+            lane = _Lane(kb, self.cap, self.max_segments, self.device, params)
+            self.lanes[kb].append(lane)
+            lane.busy = True
+            return lane
+        return None
+
+    def release_lane(self, lane):
+        lane.busy = False
+
+    def launch(self, lane, reqs):
+        torch = self.torch
+        outs = []
+        with torch.cuda.stream(lane.stream):
+            pos = 0
+            offs = lane.off_host.numpy()
+            offs[0] = 0
+            for i, r in enumerate(reqs):
+                lane.stream.wait_event(r.ready_event)
+                if r.n:
+                    lane.keys[pos:pos + r.n].copy_(r.keys, non_blocking=True)
+                    r.keys.record_stream(lane.stream)
+                pos += r.n
+                offs[i + 1] = pos
+            offs[len(reqs) + 1:] = pos      # the unused segments are empty
+            lane.off_dev.copy_(lane.off_host, non_blocking=True)
+            lane.pay[:pos].copy_(lane.iota[:pos], non_blocking=True)
+            lane.plan.sort(lane.keys, lane.pay, lane.off_dev, stream=lane.stream)
+            start = 0
+            for r in reqs:
+                k = lane.keys[start:start + r.n].clone()
+                p = lane.pay[start:start + r.n] - start
+                outs.append((k, p))
+                start += r.n
+            lane.done.record(lane.stream)
+        return (lane, outs)
+
+    def poll(self, handle) -> bool:
+        return handle[0].done.query()
+
+    def collect(self, handle):
+        """The batch's per-request outputs.  With check_status the device's
+        status word is read back (a synchronous copy); the server builds every
+        segment table itself, so only an internal error could set it."""
+        lane, outs = handle
+        if self.check_status:
+            st = lane.plan.stats(stream=lane.stream)
+            if st["status"] != 0:
+                raise BinarError(st["status"])
+        return outs

@@ -1,0 +1,97 @@
+"""Serving loop on the device: every request's result in a mixed, batched,
+multi-stream run equals the same request sorted alone (keys and permutation,
+tolerance 0), and small ones equal the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_util import need_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def make_requests(count, seed, max_log2=17):
+    import torch
+    rng = np.random.default_rng(seed)
+    host = []
+    sizes = [0, 1, 2, 3, 255, 256, 4097] + [int(2 ** rng.uniform(8, max_log2)) for _ in range(count - 7)]
+    for i, n in enumerate(sizes):
+        w = rng.choice([4, 8, 16], p=[0.5, 0.3, 0.2])
+        s = 1000 * seed + i
+        a = {4: lambda: workloads.u32_uniform(n, s), 8: lambda: workloads.u64_zipf(n, s, 1 << 10, 1.1),
+             16: lambda: workloads.str16(n, s, 5)}[w]()
+        host.append(a)
+    dev = []
+    for a in host:
+        t = torch.from_numpy(a.view(np.int32) if a.dtype == np.uint32 else
+                             (a.view(np.int64) if a.dtype == np.uint64 else a))
+        dev.append(t.cuda())
+    return host, dev
+
+
+def alone(t):
+    import torch
+    import paper_0811_3448_amd as binar
+    k = t.clone()
+    p = torch.arange(t.shape[0], dtype=torch.int32, device=t.device)
+    if t.shape[0]:
+        binar.sort(k, p)
+    return k, p
+
+
+def check_against_alone(host, dev, results, oracle_every=10):
+    import torch
+    for i, (a, t, r) in enumerate(zip(host, dev, results)):
+        k, p = alone(t)
+        torch.cuda.synchronize()
+        assert torch.equal(r.keys, k), "request %d: keys differ from the sort alone" % i
+        assert torch.equal(r.perm, p), "request %d: permutation differs from the sort alone" % i
+        if i % oracle_every == 0 and a.shape[0] <= 20000:
+            rk, rp = oracle.sort(a, np.arange(a.shape[0], dtype=np.uint32))
+            assert np.array_equal(r.keys.cpu().numpy().view(rk.dtype).reshape(rk.shape), rk)
+            assert np.array_equal(r.perm.cpu().numpy().view(np.uint32), rp)
+
+
+def test_alone_equals_in_mix():
+    from paper_0811_3448_amd.serve import Server
+    host, dev = make_requests(160, 1)
+    print("serve mix: %d requests, %d keys" % (len(dev), sum(t.shape[0] for t in dev)), flush=True)
+    with Server(budget_bytes=1 << 30, streams=2, max_batch_keys=1 << 20, max_batch_requests=32,
+                check_status=True) as srv:
+        futs = [srv.submit(t) for t in dev]
+        res = [f.result(timeout=120) for f in futs]
+        rep = srv.report()
+    assert rep["requests"] == len(dev)
+    assert rep["batches"] < len(dev)
+    assert max(r.batch_requests for r in res) > 1
+    check_against_alone(host, dev, res)
+
+
+def test_tight_budget_queues_on_device():
+    from paper_0811_3448_amd.serve import Server, request_cost
+    host, dev = make_requests(40, 2, max_log2=15)
+    budget = 3 * max(request_cost(4 if a.dtype == np.uint32 else (8 if a.dtype == np.uint64 else 16), a.shape[0])
+                     for a in host)
+    print("serve tight budget %d bytes" % budget, flush=True)
+    with Server(budget_bytes=budget, streams=2, max_batch_keys=1 << 18, check_status=True) as srv:
+        futs = [srv.submit(t) for t in dev]
+        res = [f.result(timeout=120) for f in futs]
+        assert srv.admission.peak <= budget
+        assert srv.max_waiting > 0
+    check_against_alone(host, dev, res)
+
+
+def test_one_request_per_launch_matches():
+    from paper_0811_3448_amd.serve import Server
+    host, dev = make_requests(20, 3, max_log2=14)
+    with Server(budget_bytes=1 << 30, streams=3, max_batch_keys=1 << 16, batching=False,
+                check_status=True) as srv:
+        res = [f.result(timeout=120) for f in [srv.submit(t) for t in dev]]
+    assert all(r.batch_requests == 1 for r in res)
+    check_against_alone(host, dev, res, oracle_every=5)
