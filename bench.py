@@ -181,67 +181,78 @@ def bench_batched(args) -> int:
 
 
 def bench_serve(args) -> int:
-    """Serving workload: Poisson arrivals of sort requests, sizes log-uniform
-    in [2^8, 2^24] keys, key widths u32 / u64 / 16-byte = 50 / 30 / 20 %,
-    each answered with sorted keys and permutation.  The same arrival trace
-    runs twice: continuous batching (segmented graph replays on two streams
-    per width) and one request per launch in arrival order."""
+    """Serving workload: 10,000 sort requests with Poisson arrivals, sizes
+    lognormal (median 2^16, sigma 2 ln 2, clipped to [2^8, 2^24]), key widths
+    u32 / u64 / 16-byte strings = 50 / 30 / 20 % (strings: a lowercase prefix
+    of 0..12 bytes shared by the request, the rest lowercase), each answered
+    with sorted keys and permutation.  Keys start in pinned host memory, so
+    latency (arrival to the batch's completion event) includes the upload.
+    A saturating run (all requests at once) calibrates the rate: the timed
+    runs use 0.7 of its request rate, once with continuous batching
+    (segmented graph replays, two streams per width) and once with one
+    request per launch in arrival order."""
     import numpy as np
     import torch
+    import workloads
     from paper_0811_3448_amd import tune
     from paper_0811_3448_amd.serve import Server
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    R = args.serve_requests
+    trace = workloads.serve_requests(R, rate_per_s=1.0)     # unit rate: arrival times scale with 1/rate
+    print("bench: serve pools", file=sys.stderr, flush=True)
+    pool_n = 1 << 24
+    pools = {(4, 0): torch.from_numpy(workloads.u32_uniform(pool_n, 401).view(np.int32)).pin_memory(),
+             (8, 0): torch.from_numpy(workloads.u64_uniform(pool_n, 402).view(np.int64)).pin_memory()}
+    for L in range(13):
+        pools[(16, L)] = torch.from_numpy(workloads.str16(pool_n, 410 + L, L)).pin_memory()
     rng = np.random.default_rng(0x5E7E)
-    R, rate = args.serve_requests, args.serve_rate
-    gaps = rng.exponential(1.0 / rate, R)
-    arrivals = np.cumsum(gaps) - gaps[0]
-    sizes = np.floor(2.0 ** rng.uniform(8, 24, R)).astype(np.int64)
-    widths = rng.choice([4, 8, 16], size=R, p=[0.5, 0.3, 0.2])
-    pool_n = 1 << 25
-    pools = {4: tune.synth_keys(4, pool_n, 11, dev), 8: tune.synth_keys(8, pool_n, 12, dev),
-             16: tune.synth_keys(16, pool_n, 13, dev)}
-    starts = (rng.random(R) * (pool_n - sizes)).astype(np.int64)
-    reqs = [pools[int(w)][int(a):int(a) + int(n)] for w, a, n in zip(widths, starts, sizes)]
-    torch.cuda.synchronize()
-    total_keys = int(sizes.sum())
+    reqs = []
+    for t in trace:
+        key = (t["key_bytes"], t["prefix_len"] if t["key_bytes"] == 16 else 0)
+        start = int(rng.integers(0, pool_n - t["n"] + 1))
+        reqs.append(pools[key][start:start + t["n"]])
+    unit_arrivals = np.array([t["arrival_s"] for t in trace])
+    unit_arrivals -= unit_arrivals[0]
+    total_keys = int(sum(t["n"] for t in trace))
     cache = tune.TuneCache(arch=tune.device_arch())
 
     def lookup(kb, cap):
         return cache.lookup(kb, True, cap, True, max_distance=4)
 
-    def run(batching):
+    def run(batching, rate):
         srv = Server(budget_bytes=args.serve_budget_gib << 30, streams=2, max_batch_keys=1 << 25,
                      max_batch_requests=1024, batching=batching, params_lookup=lookup)
-        # warm the lanes (first batch of each lane captures its graph)
-        warm = [srv.submit(pools[w][:4096]) for w in (4, 8, 16) for _ in range(2)]
+        warm = [srv.submit(pools[k][:4096]) for k in ((4, 0), (8, 0), (16, 0)) for _ in range(2)]
         for f in warm:
             f.result()
         srv.records.clear()
-        done = []
+        srv.batches = 0
         t0 = time.perf_counter()
         for i in range(R):
-            delay = t0 + arrivals[i] - time.perf_counter()
-            if delay > 0:
-                time.sleep(delay)
-            f = srv.submit(reqs[i])
-            f.add_done_callback(lambda f: done.append(1))
-            if i % 500 == 0:
-                print("bench: serve %s submitted %d/%d" % ("batched" if batching else "fifo", i, R),
-                      file=sys.stderr, flush=True)
+            if rate is not None:
+                delay = t0 + unit_arrivals[i] / rate - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+            srv.submit(reqs[i])
+            if i % 2000 == 0:
+                print("bench: serve %s rate %s: submitted %d/%d" % ("batched" if batching else "one-per-launch",
+                                                                    rate, i, R), file=sys.stderr, flush=True)
         srv.close()
-        rep = srv.report()
-        rep["offered_keys_s"] = total_keys / max(arrivals[-1], 1e-9)
-        return rep
+        return srv.report()
 
-    batched = run(True)
-    fifo = run(False)
+    sat = run(True, None)
+    # requests per second of the saturating run (first submission to last completion)
+    rate = 0.7 * sat["throughput_keys_s"] / (total_keys / R)
+    batched = run(True, rate)
+    fifo = run(False, rate)
 
     def fmt(rep):
         return {"p50_ms": round(rep["p50_s"] * 1e3, 3), "p99_ms": round(rep["p99_s"] * 1e3, 3),
                 "max_ms": round(rep["max_s"] * 1e3, 3),
                 "throughput_gkeys_s": round(rep["throughput_keys_s"] / 1e9, 3),
+                "requests_per_s": round(rep["requests"] * rep["throughput_keys_s"] / rep["keys"], 1),
                 "batches": rep["batches"], "requests": rep["requests"],
                 "peak_admitted_gib": round(rep["peak_admitted_bytes"] / 2 ** 30, 3),
                 "max_waiting": rep["max_waiting"]}
@@ -251,11 +262,12 @@ def bench_serve(args) -> int:
         "steps": 1, "warmup": 1, "ms_per_step": round(total_keys / batched["throughput_keys_s"] * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32/u64/u8x16",
         "data": "synthetic",
-        "config": {"workload": "serve_c5: %d requests, Poisson %.0f req/s, sizes log-uniform 2^8..2^24, "
-                               "u32/u64/16 B = 50/30/20 %%, u32 index payload" % (R, rate),
-                   "requests": R, "keys": total_keys, "offered_gkeys_s": round(batched["offered_keys_s"] / 1e9, 3),
+        "config": {"workload": "serve_c5: %d requests, Poisson at 0.7 x saturated rate, sizes lognormal "
+                               "(median 2^16, sigma 2 ln 2) in [2^8, 2^24], u32/u64/16 B = 50/30/20 %%, "
+                               "keys in pinned host memory, u32 index payload" % R,
+                   "requests": R, "keys": total_keys, "rate_req_s": round(rate, 1),
                    "budget_gib": args.serve_budget_gib},
-        "batched": fmt(batched), "one_request_per_launch": fmt(fifo),
+        "saturated": fmt(sat), "batched": fmt(batched), "one_request_per_launch": fmt(fifo),
     }
     print(json.dumps(result), flush=True)
     return 0
@@ -274,9 +286,8 @@ def main() -> int:
     ap.add_argument("--finish-max", type=int, default=0)
     ap.add_argument("--offsets", type=int, default=0, help="1 = chunk prefixes, 2 = decoupled look-back")
     ap.add_argument("--untuned", action="store_true", help="ignore the autotune cache: library defaults")
-    ap.add_argument("--serve-requests", type=int, default=3000)
-    ap.add_argument("--serve-rate", type=float, default=4000.0, help="Poisson arrival rate, requests/s")
-    ap.add_argument("--serve-budget-gib", type=int, default=24)
+    ap.add_argument("--serve-requests", type=int, default=10000)
+    ap.add_argument("--serve-budget-gib", type=int, default=32)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:

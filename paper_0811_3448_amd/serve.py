@@ -1,7 +1,8 @@
 """Serving loop for sort requests on one GPU.
 
-Requests (device tensors of keys: 4-byte, 8-byte or 16-byte, see
-``key_bytes_of``) arrive over time through ``Server.submit`` and are answered
+Requests (tensors of keys: 4-byte, 8-byte or 16-byte, see ``key_bytes_of``;
+on the device, or in pinned host memory, which the batch uploads) arrive over
+time through ``Server.submit`` and are answered
 through a ``concurrent.futures.Future`` with the sorted keys and the stable
 sorting permutation (int32 holding uint32 indices into the request).
 
@@ -17,7 +18,8 @@ sorting permutation (int32 holding uint32 indices into the request).
   A lane takes up to ``max_batch_keys`` keys and ``max_batch_requests``
   requests; whatever has been admitted when a lane frees up goes in.
 * Completion: when a lane's batch has finished, each request's results are
-  already in tensors of its own; its budget is released and its Future set.
+  views of that batch's output tensors (keys, permutation); its budget is
+  released and its Future set.
 * Cancelling a Future before its batch starts frees its budget.
 
 One scheduler thread does admission, packing, launches and completion; the
@@ -328,10 +330,15 @@ class DeviceBackend:
         self.torch.cuda.set_device(self.device)
 
     def mark_ready(self, keys):
-        """Event on the submitting thread's current stream: the lane waits
-        for it before reading the request's keys."""
-        if not keys.is_cuda or keys.device != self.device or not keys.is_contiguous():
-            raise ValueError("keys must be a contiguous tensor on %s" % self.device)
+        """Device keys: an event on the submitting thread's current stream,
+        which the lane waits for before reading them.  Host keys (pinned
+        memory, for an asynchronous upload) need none."""
+        if not keys.is_contiguous():
+            raise ValueError("keys must be contiguous")
+        if not keys.is_cuda:
+            return None
+        if keys.device != self.device:
+            raise ValueError("keys must live on %s or in host memory" % self.device)
         ev = self.torch.cuda.Event()
         ev.record()
         return ev
@@ -360,21 +367,28 @@ class DeviceBackend:
             offs = lane.off_host.numpy()
             offs[0] = 0
             for i, r in enumerate(reqs):
-                lane.stream.wait_event(r.ready_event)
+                if r.ready_event is not None:
+                    lane.stream.wait_event(r.ready_event)
                 if r.n:
                     lane.keys[pos:pos + r.n].copy_(r.keys, non_blocking=True)
-                    r.keys.record_stream(lane.stream)
+                    if r.keys.is_cuda:
+                        r.keys.record_stream(lane.stream)
                 pos += r.n
                 offs[i + 1] = pos
-            offs[len(reqs) + 1:] = pos      # the unused segments are empty
+            m = len(reqs)
+            offs[m + 1:] = pos              # the unused segments are empty
             lane.off_dev.copy_(lane.off_host, non_blocking=True)
             lane.pay[:pos].copy_(lane.iota[:pos], non_blocking=True)
             lane.plan.sort(lane.keys, lane.pay, lane.off_dev, stream=lane.stream)
+            # one output pair per batch; each request gets views of its range,
+            # its permutation made request-local by subtracting its start
+            out_keys = lane.keys[:pos].clone()
+            starts = lane.off_dev[:m]
+            lens = lane.off_dev[1:m + 1] - starts
+            out_perm = lane.pay[:pos] - torch.repeat_interleave(starts, lens, output_size=pos)
             start = 0
             for r in reqs:
-                k = lane.keys[start:start + r.n].clone()
-                p = lane.pay[start:start + r.n] - start
-                outs.append((k, p))
+                outs.append((out_keys[start:start + r.n], out_perm[start:start + r.n]))
                 start += r.n
             lane.done.record(lane.stream)
         return (lane, outs)

@@ -62,9 +62,11 @@ def test_alone_equals_in_mix():
     from paper_0811_3448_amd.serve import Server
     host, dev = make_requests(160, 1)
     print("serve mix: %d requests, %d keys" % (len(dev), sum(t.shape[0] for t in dev)), flush=True)
+    # every third request comes from pinned host memory and is uploaded by its batch
+    subs = [t.cpu().pin_memory() if i % 3 == 1 else t for i, t in enumerate(dev)]
     with Server(budget_bytes=1 << 30, streams=2, max_batch_keys=1 << 20, max_batch_requests=32,
                 check_status=True) as srv:
-        futs = [srv.submit(t) for t in dev]
+        futs = [srv.submit(t) for t in subs]
         res = [f.result(timeout=120) for f in futs]
         rep = srv.report()
     assert rep["requests"] == len(dev)
