@@ -40,30 +40,28 @@ int hip_fail(const char *what, hipError_t e) {
 
 size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
 
-// LDS-finish classes: a block of FIN_BT threads, keys per thread of each
-// class, per key width (largest class: 8192 keys, 5120 for 16-byte keys).
-constexpr int FIN_BT = 256;
 // The digit count streams keys at full bandwidth: big blocks, so that even one
 // block per CU (the 8192-key tile grid) keeps enough loads in flight.
 constexpr int HIST_BT = 1024;
+
+// LDS-finish classes per key width: (threads per block, keys per thread);
+// capacities 1024, 3072, 5120, 8192 keys (16-byte keys: 1024, 2048, 3072,
+// 5120).  Small classes use 256-thread blocks (a short segment leaves most of
+// a big block idle), the large ones 512.
 template <int KB>
-struct FinItems;
-template <>
-struct FinItems<4> {
-    static constexpr int v[NCLASS] = {4, 12, 20, 32};
+struct FinShape {
+    static constexpr int bt[NCLASS] = {256, 256, 512, 512};
+    static constexpr int items[NCLASS] = {4, 12, 10, 16};
 };
 template <>
-struct FinItems<8> {
-    static constexpr int v[NCLASS] = {4, 12, 20, 32};
-};
-template <>
-struct FinItems<16> {
-    static constexpr int v[NCLASS] = {4, 8, 12, 20};
+struct FinShape<16> {
+    static constexpr int bt[NCLASS] = {256, 256, 512, 512};
+    static constexpr int items[NCLASS] = {4, 8, 6, 10};
 };
 
 uint32_t fin_cap(uint32_t kb, int c) {
-    const int *v = (kb == 16) ? FinItems<16>::v : FinItems<4>::v;
-    return (uint32_t)(FIN_BT * v[c]);
+    return kb == 16 ? (uint32_t)(FinShape<16>::bt[c] * FinShape<16>::items[c])
+                    : (uint32_t)(FinShape<4>::bt[c] * FinShape<4>::items[c]);
 }
 
 // Scatter tiles: (threads per block, keys per thread) per tile size.
@@ -342,6 +340,16 @@ uint32_t grid_for(F fn, uint32_t work_items, int block = THREADS) {
     return std::max(1u, std::min(g, work_items));
 }
 
+template <int KB, bool PAY, int C>
+void launch_finish(const Work &w, const Layout &L, hipStream_t st) {
+    constexpr int BT = FinShape<KB>::bt[C], IT = FinShape<KB>::items[C];
+    if (!L.max_fin[C]) return;
+    static const char *names[NCLASS] = {"k_finish0", "k_finish1", "k_finish2", "k_finish3"};
+    Timed tm(st, names[C], -1);
+    hipLaunchKernelGGL((k_finish<KB, BT, IT, PAY>), dim3(grid_for(k_finish<KB, BT, IT, PAY>, L.max_fin[C], BT)),
+                       dim3(BT), 0, st, w, C);
+}
+
 template <int KB, int K, int TILE, bool PAY, bool LB>
 int enqueue(Work w, const Layout &L, const uint32_t *seg_off, uint32_t nseg, uint32_t n, hipStream_t st) {
     constexpr int SBT = ScatterShape<TILE>::BT, SIT = ScatterShape<TILE>::ITEMS;
@@ -388,32 +396,10 @@ int enqueue(Work w, const Layout &L, const uint32_t *seg_off, uint32_t nseg, uin
         hipLaunchKernelGGL((k_copyback<KB, PAY>), dim3(grid_for(k_copyback<KB, PAY>, L.max_cpy)), dim3(THREADS), 0,
                            st, w);
     }
-    constexpr int I0 = FinItems<KB>::v[0], I1 = FinItems<KB>::v[1], I2 = FinItems<KB>::v[2],
-                  I3 = FinItems<KB>::v[3];
-    if (L.max_fin[0]) {
-        Timed tm(st, "k_finish0", -1);
-        hipLaunchKernelGGL((k_finish<KB, FIN_BT, I0, PAY>),
-                           dim3(grid_for(k_finish<KB, FIN_BT, I0, PAY>, L.max_fin[0], FIN_BT)), dim3(FIN_BT), 0, st,
-                           w, 0);
-    }
-    if (L.max_fin[1]) {
-        Timed tm(st, "k_finish1", -1);
-        hipLaunchKernelGGL((k_finish<KB, FIN_BT, I1, PAY>),
-                           dim3(grid_for(k_finish<KB, FIN_BT, I1, PAY>, L.max_fin[1], FIN_BT)), dim3(FIN_BT), 0, st,
-                           w, 1);
-    }
-    if (L.max_fin[2]) {
-        Timed tm(st, "k_finish2", -1);
-        hipLaunchKernelGGL((k_finish<KB, FIN_BT, I2, PAY>),
-                           dim3(grid_for(k_finish<KB, FIN_BT, I2, PAY>, L.max_fin[2], FIN_BT)), dim3(FIN_BT), 0, st,
-                           w, 2);
-    }
-    if (L.max_fin[3]) {
-        Timed tm(st, "k_finish3", -1);
-        hipLaunchKernelGGL((k_finish<KB, FIN_BT, I3, PAY>),
-                           dim3(grid_for(k_finish<KB, FIN_BT, I3, PAY>, L.max_fin[3], FIN_BT)), dim3(FIN_BT), 0, st,
-                           w, 3);
-    }
+    launch_finish<KB, PAY, 0>(w, L, st);
+    launch_finish<KB, PAY, 1>(w, L, st);
+    launch_finish<KB, PAY, 2>(w, L, st);
+    launch_finish<KB, PAY, 3>(w, L, st);
     BINAR_HIP_TRY(hipGetLastError());
     return BINAR_OK;
 }

@@ -1025,6 +1025,118 @@ __global__ __launch_bounds__(BT) void k_scatter(Work w, int L) {
 // One workgroup per small segment (at most BT * ITEMS keys): find the bits
 // that vary inside it (AND/OR), sort stably by them with
 // least-significant-first LDS passes of up to 8 bits, write to A.
+// Copies between a segment's range [g0, g1) of a global buffer and LDS
+// (element g of the range at lds[g - g0]): the 16-byte aligned body as whole
+// vectors, the unaligned head and tail one element at a time.  Loads issue
+// every vector of the thread before the first LDS write, so the whole range
+// is in flight at once; NV bounds the vectors per thread.
+template <int VN, int ES>
+__device__ __forceinline__ void aligned_body(const void *base, size_t g0, size_t g1, size_t &b0, size_t &b1) {
+    const size_t mis = ((16u - (reinterpret_cast<uintptr_t>(base) & 15u)) & 15u) / ES;
+    b0 = min(g1, g0 + ((mis + VN - (g0 % VN)) % VN));
+    b1 = b0 + (g1 - b0) / VN * VN;
+}
+
+template <int KB, int NV, int BT>
+__device__ __forceinline__ void fin_load_keys(const void *src, size_t g0, size_t g1, typename KeyT<KB>::V *lds,
+                                              typename KeyT<KB>::V &a, typename KeyT<KB>::V &o) {
+    using KT = KeyT<KB>;
+    using V = typename KT::V;
+    constexpr int VN = Vec<KB>::N;
+    size_t b0, b1;
+    aligned_body<VN, KB>(src, g0, g1, b0, b1);
+    V v[NV][VN];
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+        const size_t x = b0 + ((size_t)u * BT + threadIdx.x) * VN;
+        if (x < b1) load_vec<KB>(src, x, v[u]);
+    }
+    for (size_t i = g0 + threadIdx.x; i < b0; i += BT) {
+        const V k = KT::load(src, i);
+        lds[i - g0] = k;
+        a = KT::vand(a, k);
+        o = KT::vor(o, k);
+    }
+    for (size_t i = b1 + threadIdx.x; i < g1; i += BT) {
+        const V k = KT::load(src, i);
+        lds[i - g0] = k;
+        a = KT::vand(a, k);
+        o = KT::vor(o, k);
+    }
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+        const size_t x = b0 + ((size_t)u * BT + threadIdx.x) * VN;
+        if (x < b1) {
+#pragma unroll
+            for (int q = 0; q < VN; ++q) {
+                lds[x - g0 + q] = v[u][q];
+                a = KT::vand(a, v[u][q]);
+                o = KT::vor(o, v[u][q]);
+            }
+        }
+    }
+}
+
+template <int NV, int BT>
+__device__ __forceinline__ void fin_load_pay(const uint32_t *src, size_t g0, size_t g1, uint32_t *lds) {
+    size_t b0, b1;
+    aligned_body<4, 4>(src, g0, g1, b0, b1);
+    uint4 v[NV];
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+        const size_t x = b0 + ((size_t)u * BT + threadIdx.x) * 4;
+        if (x < b1) v[u] = *reinterpret_cast<const uint4 *>(src + x);
+    }
+    for (size_t i = g0 + threadIdx.x; i < b0; i += BT) lds[i - g0] = src[i];
+    for (size_t i = b1 + threadIdx.x; i < g1; i += BT) lds[i - g0] = src[i];
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+        const size_t x = b0 + ((size_t)u * BT + threadIdx.x) * 4;
+        if (x < b1) {
+            uint32_t *d = lds + (x - g0);
+            d[0] = v[u].x;
+            d[1] = v[u].y;
+            d[2] = v[u].z;
+            d[3] = v[u].w;
+        }
+    }
+}
+
+template <int KB, int BT>
+__device__ __forceinline__ void fin_store_keys(void *dst, size_t g0, size_t g1, const typename KeyT<KB>::V *lds) {
+    using KT = KeyT<KB>;
+    constexpr int VN = Vec<KB>::N;
+    size_t b0, b1;
+    aligned_body<VN, KB>(dst, g0, g1, b0, b1);
+    for (size_t i = g0 + threadIdx.x; i < b0; i += BT) KT::store(dst, i, lds[i - g0]);
+    for (size_t i = b1 + threadIdx.x; i < g1; i += BT) KT::store(dst, i, lds[i - g0]);
+    for (size_t x = b0 + (size_t)threadIdx.x * VN; x < b1; x += (size_t)BT * VN) {
+        const typename KT::V *s = lds + (x - g0);
+        if constexpr (KB == 4) {
+            *reinterpret_cast<uint4 *>(reinterpret_cast<uint32_t *>(dst) + x) = make_uint4(s[0], s[1], s[2], s[3]);
+        } else if constexpr (KB == 8) {
+            ulonglong2 r;
+            r.x = s[0];
+            r.y = s[1];
+            *reinterpret_cast<ulonglong2 *>(reinterpret_cast<uint64_t *>(dst) + x) = r;
+        } else {
+            KT::store(dst, x, s[0]);
+        }
+    }
+}
+
+template <int BT>
+__device__ __forceinline__ void fin_store_pay(uint32_t *dst, size_t g0, size_t g1, const uint32_t *lds) {
+    size_t b0, b1;
+    aligned_body<4, 4>(dst, g0, g1, b0, b1);
+    for (size_t i = g0 + threadIdx.x; i < b0; i += BT) dst[i] = lds[i - g0];
+    for (size_t i = b1 + threadIdx.x; i < g1; i += BT) dst[i] = lds[i - g0];
+    for (size_t x = b0 + (size_t)threadIdx.x * 4; x < b1; x += (size_t)BT * 4) {
+        const uint32_t *s = lds + (x - g0);
+        *reinterpret_cast<uint4 *>(dst + x) = make_uint4(s[0], s[1], s[2], s[3]);
+    }
+}
+
 template <int KB, int BT, int ITEMS, bool PAY>
 struct FinishLds {
     using V = typename KeyT<KB>::V;
@@ -1039,8 +1151,19 @@ struct FinishLds {
     unsigned long long ao[NW][4];
 };
 
+// Waves per SIMD that the register budget must allow for a finish class:
+// as many blocks as fit a CU by LDS (160 KiB), at most 4 waves (a higher
+// floor makes the keys-only classes spill).
 template <int KB, int BT, int ITEMS, bool PAY>
-__global__ __launch_bounds__(BT) void k_finish(Work w, int cls) {
+struct FinOcc {
+    static constexpr int blocks = (160 * 1024) / (int)sizeof(FinishLds<KB, BT, ITEMS, PAY>);
+    static constexpr int lds_waves = (blocks * (BT / WAVE) + 3) / 4;
+    static constexpr int waves = lds_waves < 4 ? lds_waves : 4;
+};
+
+template <int KB, int BT, int ITEMS, bool PAY>
+__global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(FinOcc<KB, BT, ITEMS, PAY>::waves)))
+void k_finish(Work w, int cls) {
     using KT = KeyT<KB>;
     using V = typename KT::V;
     constexpr int KL = 8;
@@ -1071,18 +1194,11 @@ __global__ __launch_bounds__(BT) void k_finish(Work w, int cls) {
         }
         st_keys += len;
         ++st_segs;
-        const char *src = static_cast<const char *>(w.keys[parity]) + (size_t)fe.begin * KB;
-        const uint32_t *psrc = PAY ? w.pay[parity] + fe.begin : nullptr;
-
         // load into LDS in input order, AND/OR on the way
         V a = KT::ones(), o = KT::zero();
-        for (uint32_t p = threadIdx.x; p < len; p += BT) {
-            const V k = KT::load(src, p);
-            S.keys[p] = k;
-            if (PAY) S.pay[p] = psrc[p];
-            a = KT::vand(a, k);
-            o = KT::vor(o, k);
-        }
+        fin_load_keys<KB, (CAP + Vec<KB>::N * BT - 1) / (Vec<KB>::N * BT), BT>(
+            w.keys[parity], fe.begin, (size_t)fe.begin + len, S.keys, a, o);
+        if constexpr (PAY) fin_load_pay<(CAP + 4 * BT - 1) / (4 * BT), BT>(w.pay[parity], fe.begin, (size_t)fe.begin + len, S.pay);
         Canon ca = KT::canon(a), co = KT::canon(o);
 #pragma unroll
         for (int off = 1; off < WAVE; off <<= 1) {
@@ -1168,12 +1284,8 @@ __global__ __launch_bounds__(BT) void k_finish(Work w, int cls) {
             for (int i = lane; i < R; i += WAVE) S.wh[wv][i] = 0u;
             hib = last_set_below(diff, bitpos, lo);
         }
-        char *dst = static_cast<char *>(w.keys[0]) + (size_t)fe.begin * KB;
-        uint32_t *pdst = PAY ? w.pay[0] + fe.begin : nullptr;
-        for (uint32_t p = threadIdx.x; p < len; p += BT) {
-            KT::store(dst, p, S.keys[p]);
-            if (PAY) pdst[p] = S.pay[p];
-        }
+        fin_store_keys<KB, BT>(w.keys[0], fe.begin, (size_t)fe.begin + len, S.keys);
+        if constexpr (PAY) fin_store_pay<BT>(w.pay[0], fe.begin, (size_t)fe.begin + len, S.pay);
         __syncthreads();
     }
     if (threadIdx.x == 0 && st_segs) {
