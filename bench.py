@@ -84,6 +84,29 @@ def describe_params(binar, kb, has_pay, params, source):
             "offsets": "decoupled look-back" if r.offsets == 2 else "chunk prefixes", "params_from": source}
 
 
+def per_array_calls(binar, torch, kbuf, pbuf, restore, offs, S, params, stream, np):
+    """The same arrays sorted by one library call each, all enqueued on the
+    stream with one workspace: (GPU ms between events, host seconds)."""
+    ws = binar.Workspace(binar.workspace_bytes(4, int(max(b - a for a, b in zip(offs, offs[1:]))), True, 1,
+                                               params))
+    restore()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for s in range(S):
+        a, b = offs[s], offs[s + 1]
+        if b - a > 1:
+            binar.sort(kbuf[a:b], pbuf[a:b], workspace=ws, params=params)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1), time.perf_counter() - t0
+
+
+def offs_of(off_np):
+    return off_np.astype("int64").tolist()
+
+
 def bench_batched(args) -> int:
     """Batched workload: 100,000 lognormal segments of u32 keys (+ global
     index payload), about 2^27 keys.  One HIP-graph replay of the segmented
@@ -144,22 +167,11 @@ def bench_batched(args) -> int:
     st_e = binar.stats(ws_b)
     del ws_b
 
-    # one library call per array, all enqueued on the stream with one workspace
-    ws = binar.Workspace(binar.workspace_bytes(4, int(np.diff(off_np).max()), True, 1, params))
-    offs = off_np.astype(np.int64).tolist()
-    restore()
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record(stream)
-    for s in range(S):
-        a, b = offs[s], offs[s + 1]
-        if b - a > 1:
-            binar.sort(kbuf[a:b], pbuf[a:b], workspace=ws, params=params)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    per_array_ms = e0.elapsed_time(e1)
-    per_array_wall = time.perf_counter() - t0
+    if args.no_per_array:
+        per_array_ms = per_array_wall = None
+    else:
+        per_array_ms, per_array_wall = per_array_calls(binar, torch, kbuf, pbuf, restore, offs_of(off_np),
+                                                       S, params, stream, np)
     result = {
         "metric": "Gkeys/s, batched segmented sort of 100,000 arrays in one graph replay",
         "value": round(n / (graph_ms * 1e-3) / 1e9, 3), "unit": "Gkeys/s", "n_gpus": 1,
@@ -169,9 +181,10 @@ def bench_batched(args) -> int:
         "config": {"workload": "batched_u32_100k: %d lognormal segments (median 1024, sigma 0.7356), %d u32 keys "
                                "+ u32 index payload" % (S, n), "segments": S, "n": n,
                    **describe_params(binar, 4, True, params, source)},
-        "per_array_calls": {"ms": round(per_array_ms, 2), "gkeys_s": round(n / (per_array_ms * 1e-3) / 1e9, 3),
-                            "host_wall_s": round(per_array_wall, 2)},
-        "speedup_vs_per_array": round(per_array_ms / graph_ms, 2),
+        "per_array_calls": None if per_array_ms is None else {
+            "ms": round(per_array_ms, 2), "gkeys_s": round(n / (per_array_ms * 1e-3) / 1e9, 3),
+            "host_wall_s": round(per_array_wall, 2)},
+        "speedup_vs_per_array": None if per_array_ms is None else round(per_array_ms / graph_ms, 2),
         "finish_segments": st["finish_segments"], "passes": st["passes"],
         "eager_kernels_ms": kernels,
         "finish_class_segments": st_e["finish_class_segments"], "finish_class_keys": st_e["finish_class_keys"],
@@ -286,6 +299,7 @@ def main() -> int:
     ap.add_argument("--finish-max", type=int, default=0)
     ap.add_argument("--offsets", type=int, default=0, help="1 = chunk prefixes, 2 = decoupled look-back")
     ap.add_argument("--untuned", action="store_true", help="ignore the autotune cache: library defaults")
+    ap.add_argument("--no-per-array", action="store_true", help="batched workload: skip the per-array comparison")
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--serve-budget-gib", type=int, default=32)
     args = ap.parse_args()
@@ -389,6 +403,25 @@ def main() -> int:
     avg_ms = dom_ms / dom_launches
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
 
+    # per global pass: digit count + offsets + scatter, against the pass's
+    # algorithmic bytes (keys read by the count, keys + payload moved); then
+    # the LDS finish as the last stage
+    per_pass = []
+    for j in range(16):
+        ms = sum(m for nm, ps, m in launches if ps == j and nm in ("k_hist", "k_pscan", "k_plan", "k_scatter")) / K
+        b = kb * st["hist_keys"][j] + 2 * (kb + pb) * st["moved"][j]
+        if b == 0:
+            continue
+        per_pass.append({"pass": j, "ms": round(ms, 4), "bytes": int(b),
+                         "gbs": round(b / (ms * 1e-3) / 1e9, 1),
+                         "frac": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)})
+    fin_ms = sum(m for nm, ps, m in launches if nm.startswith("k_finish")) / K
+    fin_b = 2 * (kb + pb) * st["finish_keys"]
+    if fin_b:
+        per_pass.append({"pass": "finish", "ms": round(fin_ms, 4), "bytes": int(fin_b),
+                         "gbs": round(fin_b / (fin_ms * 1e-3) / 1e9, 1),
+                         "frac": round(fin_b / (fin_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)})
+
     ms_per_step = gpu_ms / K
     value = n * K / (gpu_ms * 1e-3) / 1e9
     result = {
@@ -417,6 +450,7 @@ def main() -> int:
                           "frac": round(total_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "kernels_ms_per_step": {nm: round(v[0] / K, 4) for nm, v in sorted(agg.items())},
         "passes": st["passes"],
+        "per_pass": per_pass,
         "moved_per_pass": [x for x in st["moved"] if x],
         "wall_s": round(wall, 4),
     }

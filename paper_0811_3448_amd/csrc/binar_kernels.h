@@ -174,49 +174,57 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *tmp, u
 // Stable rank of every key of a wave's ITEMS steps (64 consecutive keys per
 // step) among the keys with the same digit: keys of earlier steps of this
 // wave + earlier lanes of this step.
-//   tbl  : this wave's two tables of R 64-bit lane masks in LDS (zero on
-//          entry and exit)
+//   tbl  : this wave's table of R 64-bit lane masks in LDS (zero on entry
+//          and exit)
 //   whist: this wave's R counters in LDS (zero on entry; the wave's digit
 //          counts on exit)
-// Steps go in groups of P (1 or 2), step j on table j % P: every lane
-// ORs its lane bit into tbl[digit] and reads the word back -- the mask of
-// the lanes holding its digit -- then clears it.  The highest lane of each
-// mask adds the group size to whist[digit] with an LDS atomic and the others
-// take the old value from it.  A wave's LDS operations execute in issue
-// order, so the counters advance step by step and the ranks follow the input
-// order; P tables let the P steps of a group overlap.  FULL: every
-// key of the tile is valid.
-template <int R, int P, int ITEMS, bool FULL>
+// For each step every lane ORs its lane bit into tbl[digit] and reads the
+// word back -- the mask of the lanes holding its digit -- then clears it.
+// The highest lane of each mask adds the group size to whist[digit] with an
+// LDS atomic and the others take the old value from it.  A wave's LDS
+// operations execute in issue order, so one table serves every step and the
+// counters advance step by step: the ranks follow the input order.  Steps go
+// in groups of G whose operations are issued back to back (masks of all G
+// steps, then all G counter updates, then all G broadcasts), so a group
+// waits for the LDS three times instead of three times per step.  FULL:
+// every key of the tile is valid.
+constexpr int RANK_GROUP = 2;  // steps per group of wave_rank
+
+template <int R, int G, int ITEMS, bool FULL>
 __device__ __forceinline__ void wave_rank(const uint32_t (&dg)[ITEMS], uint32_t ebase, uint32_t len,
                                           unsigned long long *tbl, uint32_t *whist, uint32_t (&rnk)[ITEMS]) {
     const unsigned long long me = 1ull << lane_id();
 #pragma unroll
-    for (int j0 = 0; j0 < ITEMS; j0 += P) {
-        bool valid[P];
-        unsigned long long m[P];
+    for (int j0 = 0; j0 < ITEMS; j0 += G) {
+        bool valid[G];
+        unsigned long long m[G];
 #pragma unroll
-        for (int g = 0; g < P; ++g) {
-            valid[g] = (j0 + g < ITEMS) && (FULL || ebase + (uint32_t)(j0 + g) * WAVE < len);
-            if (valid[g]) atomicOr(&tbl[g * R + dg[j0 + g]], me);
+        for (int g = 0; g < G; ++g) {
+            const int j = j0 + g;
+            valid[g] = (j < ITEMS) && (FULL || ebase + (uint32_t)j * WAVE < len);
+            m[g] = 0ull;
+            if (valid[g]) {
+                atomicOr(&tbl[dg[j]], me);
+                m[g] = tbl[dg[j]];
+                tbl[dg[j]] = 0ull;
+            }
         }
+        uint32_t lead[G], got[G];
 #pragma unroll
-        for (int g = 0; g < P; ++g) m[g] = valid[g] ? tbl[g * R + dg[j0 + g]] : 0ull;
-#pragma unroll
-        for (int g = 0; g < P; ++g)
-            if (valid[g]) tbl[g * R + dg[j0 + g]] = 0ull;
-        uint32_t lead[P], got[P];
-#pragma unroll
-        for (int g = 0; g < P; ++g) {
-            if (j0 + g >= ITEMS) break;
-            const uint32_t r = lanes_below(m[g]);
-            const uint32_t c = (uint32_t)__popcll(m[g]);
-            lead[g] = 63u - (uint32_t)__clzll(m[g] | 1ull);
-            rnk[j0 + g] = r;
+        for (int g = 0; g < G; ++g) {
+            const int j = j0 + g;
             got[g] = 0u;
-            if (valid[g] && r + 1u == c) got[g] = atomicAdd(&whist[dg[j0 + g]], c);
+            lead[g] = 0u;
+            if (j < ITEMS) {
+                const uint32_t r = lanes_below(m[g]);
+                const uint32_t c = (uint32_t)__popcll(m[g]);
+                lead[g] = 63u - (uint32_t)__clzll(m[g] | 1ull);
+                rnk[j] = r;
+                if (valid[g] && r + 1u == c) got[g] = atomicAdd(&whist[dg[j]], c);
+            }
         }
 #pragma unroll
-        for (int g = 0; g < P; ++g)
+        for (int g = 0; g < G; ++g)
             if (j0 + g < ITEMS) rnk[j0 + g] += (uint32_t)__shfl((int)got[g], (int)lead[g], WAVE);
     }
 }
@@ -776,7 +784,7 @@ __device__ __forceinline__ void scatter_tile(const Work &w, int L, ScatterLds<KB
     const uint32_t ebase = (uint32_t)wv * ITEMS * WAVE + (uint32_t)lane;
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) dg[j] = KT::digit(key[j], bitpos, wbits);
-    wave_rank<R, 1, ITEMS, FULL>(dg, ebase, tlen, &S.tbl[wv][0][0], &S.wh[wv][0], rnk);
+    wave_rank<R, RANK_GROUP, ITEMS, FULL>(dg, ebase, tlen, &S.tbl[wv][0][0], &S.wh[wv][0], rnk);
     __syncthreads();
     // per digit: staged offset of each wave's keys, tile count, global offset
     uint32_t tcnt = 0;
@@ -1245,7 +1253,7 @@ void k_finish(Work w, int cls) {
                 key[j] = (e < len) ? S.keys[e] : KT::zero();
                 dg[j] = KT::digit(key[j], lo, wbits);
             }
-            wave_rank<R, 1, ITEMS, false>(dg, ebase, len, &S.tbl[wv][0][0], &S.wh[wv][0], rnk);
+            wave_rank<R, RANK_GROUP, ITEMS, false>(dg, ebase, len, &S.tbl[wv][0][0], &S.wh[wv][0], rnk);
             uint32_t pay[ITEMS];
 #pragma unroll
             for (int j = 0; j < ITEMS; ++j) {
