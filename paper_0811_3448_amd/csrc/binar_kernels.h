@@ -174,12 +174,14 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *tmp, u
 // Stable rank of every key of a wave's ITEMS steps (64 consecutive keys per
 // step) among the keys with the same digit: keys of earlier steps of this
 // wave + earlier lanes of this step.
-//   tbl  : this wave's table of R 64-bit lane masks in LDS (zero on entry
-//          and exit)
+//   tbl  : this wave's table of R lane masks in LDS, each two 32-bit words
+//          (lanes 0-31, lanes 32-63), 8-byte aligned (zero on entry and exit)
 //   whist: this wave's R counters in LDS (zero on entry; the wave's digit
 //          counts on exit)
-// For each step every lane ORs its lane bit into tbl[digit] and reads the
-// word back -- the mask of the lanes holding its digit -- then clears it.
+// For each step every lane ORs its lane bit into its half of tbl[digit] and
+// reads the whole 64-bit mask back -- the lanes holding its digit -- then
+// clears its half (32-bit atomics spread a wave's 64 lanes over the LDS banks
+// better than 64-bit ones).
 // The highest lane of each mask adds the group size to whist[digit] with an
 // LDS atomic and the others take the old value from it.  A wave's LDS
 // operations execute in issue order, so one table serves every step and the
@@ -192,8 +194,10 @@ constexpr int RANK_GROUP = 2;  // steps per group of wave_rank
 
 template <int R, int G, int ITEMS, bool FULL>
 __device__ __forceinline__ void wave_rank(const uint32_t (&dg)[ITEMS], uint32_t ebase, uint32_t len,
-                                          unsigned long long *tbl, uint32_t *whist, uint32_t (&rnk)[ITEMS]) {
-    const unsigned long long me = 1ull << lane_id();
+                                          uint32_t *tbl, uint32_t *whist, uint32_t (&rnk)[ITEMS]) {
+    // the 64-bit view of a mask may alias the 32-bit words it is built from
+    typedef unsigned long long __attribute__((may_alias)) mask_t;
+    const uint32_t half = (uint32_t)lane_id() >> 5, me = 1u << (lane_id() & 31);
 #pragma unroll
     for (int j0 = 0; j0 < ITEMS; j0 += G) {
         bool valid[G];
@@ -204,9 +208,9 @@ __device__ __forceinline__ void wave_rank(const uint32_t (&dg)[ITEMS], uint32_t 
             valid[g] = (j < ITEMS) && (FULL || ebase + (uint32_t)j * WAVE < len);
             m[g] = 0ull;
             if (valid[g]) {
-                atomicOr(&tbl[dg[j]], me);
-                m[g] = tbl[dg[j]];
-                tbl[dg[j]] = 0ull;
+                atomicOr(&tbl[2u * dg[j] + half], me);
+                m[g] = *reinterpret_cast<const mask_t *>(&tbl[2u * dg[j]]);
+                tbl[2u * dg[j] + half] = 0u;
             }
         }
         uint32_t lead[G], got[G];
@@ -715,7 +719,7 @@ struct ScatterLds {
     static constexpr int CR = LOOKBACK ? 1 : R;      // digits that carry
     V keys[TILE];
     uint32_t pay[PAY ? TILE : 1];
-    unsigned long long tbl[NW][P][R];  // lane masks of the wave ranking
+    alignas(8) uint32_t tbl[NW][2 * R];  // lane masks of the wave ranking
     uint32_t wh[NW][R];             // per-wave digit counts -> staged offset of (wave, digit)
     uint32_t gofs[R];               // global index of staged position 0 of digit d
     uint32_t run[R];                // chunked offsets: next global index of digit d in this piece
@@ -784,7 +788,7 @@ __device__ __forceinline__ void scatter_tile(const Work &w, int L, ScatterLds<KB
     const uint32_t ebase = (uint32_t)wv * ITEMS * WAVE + (uint32_t)lane;
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) dg[j] = KT::digit(key[j], bitpos, wbits);
-    wave_rank<R, RANK_GROUP, ITEMS, FULL>(dg, ebase, tlen, &S.tbl[wv][0][0], &S.wh[wv][0], rnk);
+    wave_rank<R, RANK_GROUP, ITEMS, FULL>(dg, ebase, tlen, &S.tbl[wv][0], &S.wh[wv][0], rnk);
     __syncthreads();
     // per digit: staged offset of each wave's keys, tile count, global offset
     uint32_t tcnt = 0;
@@ -947,7 +951,7 @@ __global__ __launch_bounds__(BT) void k_scatter(Work w, int L) {
         if (t0 >= t1) return;
     }
     for (int i = threadIdx.x; i < NW * R; i += BT) (&S.wh[0][0])[i] = 0u;
-    for (int i = threadIdx.x; i < NW * R; i += BT) (&S.tbl[0][0][0])[i] = 0ull;
+    for (int i = threadIdx.x; i < NW * 2 * R; i += BT) (&S.tbl[0][0])[i] = 0u;
     __syncthreads();
 
     V key[ITEMS];
@@ -1153,7 +1157,7 @@ struct FinishLds {
     static constexpr int NW = BT / WAVE;
     V keys[CAP];
     uint32_t pay[PAY ? CAP : 1];
-    unsigned long long tbl[NW][1][R];
+    alignas(8) uint32_t tbl[NW][2 * R];
     uint32_t wh[NW][R];
     uint32_t tmp[NW];
     unsigned long long ao[NW][4];
@@ -1187,7 +1191,7 @@ void k_finish(Work w, int cls) {
     const int wv = threadIdx.x / WAVE, lane = lane_id();
     const uint32_t ebase = (uint32_t)wv * ITEMS * WAVE + (uint32_t)lane;
     for (int i = threadIdx.x; i < NW * R; i += BT) (&S.wh[0][0])[i] = 0u;
-    for (int i = threadIdx.x; i < NW * R; i += BT) (&S.tbl[0][0][0])[i] = 0ull;
+    for (int i = threadIdx.x; i < NW * 2 * R; i += BT) (&S.tbl[0][0])[i] = 0u;
     __syncthreads();
 
     unsigned long long st_keys = 0ull, st_segs = 0ull;  // flushed once per block
@@ -1253,7 +1257,7 @@ void k_finish(Work w, int cls) {
                 key[j] = (e < len) ? S.keys[e] : KT::zero();
                 dg[j] = KT::digit(key[j], lo, wbits);
             }
-            wave_rank<R, RANK_GROUP, ITEMS, false>(dg, ebase, len, &S.tbl[wv][0][0], &S.wh[wv][0], rnk);
+            wave_rank<R, RANK_GROUP, ITEMS, false>(dg, ebase, len, &S.tbl[wv][0], &S.wh[wv][0], rnk);
             uint32_t pay[ITEMS];
 #pragma unroll
             for (int j = 0; j < ITEMS; ++j) {

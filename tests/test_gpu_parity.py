@@ -141,3 +141,25 @@ def test_segmented_small(T):
     rk, rp = oracle.sort_segmented(keys, off, iota(n))
     assert np.array_equal(gk, rk)
     assert np.array_equal(gp, rp)
+
+
+@pytest.mark.parametrize("kb", [4, 8, 16])
+def test_finish_class_boundaries(kb):
+    """Segments exactly at and just past every LDS-finish class capacity
+    (1024, 3072, 5120, 8192 keys; 16-byte keys 1024, 2048, 3072, 5120), at
+    unaligned offsets, each finished by its class or split by a pass."""
+    caps = [1024, 2048, 3072, 5120] if kb == 16 else [1024, 3072, 5120, 8192]
+    lens = []
+    for c in caps:
+        lens += [c - 1, c, c + 1]
+    lens += [1, 2, 3, 63, 65]
+    off = np.zeros(len(lens) + 1, dtype=np.uint32)
+    off[1:] = np.cumsum(lens)
+    n = int(off[-1])
+    keys = {4: lambda: workloads.u32_uniform(n, 300), 8: lambda: workloads.u64_uniform(n, 301),
+            16: lambda: workloads.str16(n, 302, 2)}[kb]()
+    print("class boundaries kb=%d n=%d segments=%d" % (kb, n, len(lens)), flush=True)
+    gk, gp = gpu_sort_segmented(keys, off, iota(n))
+    rk, rp = oracle.sort_segmented(keys, off, iota(n))
+    assert np.array_equal(gk, rk)
+    assert np.array_equal(gp, rp)
