@@ -1157,11 +1157,158 @@ struct FinishLds {
     static constexpr int NW = BT / WAVE;
     V keys[CAP];
     uint32_t pay[PAY ? CAP : 1];
-    alignas(8) uint32_t tbl[NW][2 * R];
+    alignas(8) uint32_t tbl[NW][2 * R];  // lane masks; between passes also the list of runs to fix
     uint32_t wh[NW][R];
     uint32_t tmp[NW];
     unsigned long long ao[NW][4];
+    uint32_t long_run;
 };
+
+// Stable LDS passes over the varying bits of the segment in S with bit
+// index in [bitpos, end] (MSB-first indices), least significant window of up
+// to 8 bits first; constant windows are skipped.  The order lives in S
+// between passes.
+template <int KB, int BT, int ITEMS, bool PAY>
+__device__ __forceinline__ void lds_passes(FinishLds<KB, BT, ITEMS, PAY> &S, Canon diff, int bitpos, int end,
+                                           uint32_t len) {
+    using KT = KeyT<KB>;
+    using V = typename KT::V;
+    constexpr int KL = 8;
+    constexpr int R = 1 << KL;
+    constexpr int NW = BT / WAVE;
+    const int wv = threadIdx.x / WAVE, lane = lane_id();
+    const uint32_t ebase = (uint32_t)wv * ITEMS * WAVE + (uint32_t)lane;
+    int hib = last_set_below(diff, bitpos, end + 1);
+    while (hib >= bitpos) {
+        const int lo = max(bitpos, hib - KL + 1);
+        const int wbits = hib - lo + 1;
+        V key[ITEMS];
+        uint32_t dg[ITEMS], rnk[ITEMS];
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const uint32_t e = ebase + j * WAVE;
+            key[j] = (e < len) ? S.keys[e] : KT::zero();
+            dg[j] = KT::digit(key[j], lo, wbits);
+        }
+        wave_rank<R, RANK_GROUP, ITEMS, false>(dg, ebase, len, &S.tbl[wv][0], &S.wh[wv][0], rnk);
+        uint32_t pay[ITEMS];
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const uint32_t e = ebase + j * WAVE;
+            if (PAY) pay[j] = (e < len) ? S.pay[e] : 0u;
+        }
+        __syncthreads();
+        uint32_t tcnt = 0;
+        if (threadIdx.x < R) {
+#pragma unroll
+            for (int q = 0; q < NW; ++q) tcnt += S.wh[q][threadIdx.x];
+        }
+        uint32_t tot;
+        uint32_t acc = block_excl_scan<BT>(tcnt, S.tmp, &tot);  // every thread: it holds barriers
+        if (threadIdx.x < R) {
+#pragma unroll
+            for (int q = 0; q < NW; ++q) {
+                const uint32_t x = S.wh[q][threadIdx.x];
+                S.wh[q][threadIdx.x] = acc;
+                acc += x;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const uint32_t e = ebase + j * WAVE;
+            if (e < len) {
+                const uint32_t pos = S.wh[wv][dg[j]] + rnk[j];
+                S.keys[pos] = key[j];
+                if (PAY) S.pay[pos] = pay[j];
+            }
+        }
+        __syncthreads();
+        // each wave clears its own counters: only it touches them before
+        // the next barrier
+        for (int i = lane; i < R; i += WAVE) S.wh[wv][i] = 0u;
+        hib = last_set_below(diff, bitpos, lo);
+    }
+}
+
+// a and b agree on the bits set in m
+__device__ __forceinline__ bool canon_eq_under(Canon a, Canon b, Canon m) {
+    return (((a.hi ^ b.hi) & m.hi) | ((a.lo ^ b.lo) & m.lo)) == 0ull;
+}
+
+__device__ __forceinline__ bool canon_less(Canon a, Canon b) {
+    return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo);
+}
+
+// The segment in S is sorted stably by its bits [0, pe]: keys equal on them
+// form runs, each in input order, still to be ordered by the bits after pe
+// (the recursion on sub-arrays, done in LDS).  Each run of up to 64 keys is
+// ranked by one wave: a key's new place is the number of run members that
+// are smaller, or equal and earlier.  Returns true, with nothing of a longer
+// run moved, if some run is longer than 64 keys.
+template <int KB, int BT, int ITEMS, bool PAY>
+__device__ bool fix_runs(FinishLds<KB, BT, ITEMS, PAY> &S, int pe, uint32_t len) {
+    using KT = KeyT<KB>;
+    using V = typename KT::V;
+    constexpr int NW = BT / WAVE;
+    constexpr int CAP = BT * ITEMS;
+    constexpr uint32_t LIST = NW * 2 * (1u << 8);
+    static_assert(LIST >= CAP / 2, "run list must hold every possible run start");
+    uint32_t *list = &S.tbl[0][0];
+    const int wv = threadIdx.x / WAVE, lane = lane_id();
+    Canon pm;
+    pm.hi = pe >= 63 ? ~0ull : ~(~0ull >> (pe + 1));
+    pm.lo = pe >= 127 ? ~0ull : (pe < 64 ? 0ull : ~(~0ull >> (pe - 63)));
+    if (threadIdx.x == 0) S.long_run = 0u;
+    // run starts: first key of a run of two or more
+    auto is_start = [&](uint32_t p) -> bool {
+        if (p + 1 >= len) return false;
+        const Canon k = KT::canon(S.keys[p]);
+        if (!canon_eq_under(KT::canon(S.keys[p + 1]), k, pm)) return false;
+        return p == 0 || !canon_eq_under(KT::canon(S.keys[p - 1]), k, pm);
+    };
+    uint32_t cnt = 0;
+    for (uint32_t p = threadIdx.x; p < len; p += BT) cnt += is_start(p) ? 1u : 0u;
+    uint32_t nruns;
+    uint32_t at = block_excl_scan<BT>(cnt, S.tmp, &nruns);  // every thread: it holds barriers
+    for (uint32_t p = threadIdx.x; p < len; p += BT)
+        if (is_start(p)) list[at++] = p;
+    __syncthreads();
+    for (uint32_t r = wv; r < nruns; r += NW) {
+        const uint32_t s0 = list[r];
+        const uint32_t e = s0 + (uint32_t)lane;
+        const Canon ks = KT::canon(S.keys[s0]);
+        V k = KT::zero();
+        bool in = false;
+        if (e < len) {
+            k = S.keys[e];
+            in = canon_eq_under(KT::canon(k), ks, pm);
+        }
+        const unsigned long long m = __ballot(in);
+        const uint32_t L = (~m == 0ull) ? 64u : (uint32_t)__builtin_ctzll(~m);
+        if (L == 64u && s0 + 64u < len && canon_eq_under(KT::canon(S.keys[s0 + 64u]), ks, pm)) {
+            if (lane == 0) S.long_run = 1u;
+            continue;
+        }
+        const Canon kc = KT::canon(k);
+        uint32_t rank = 0;
+        for (uint32_t q = 0; q < L; ++q) {
+            const Canon c = KT::canon(S.keys[s0 + q]);
+            rank += (canon_less(c, kc) || (q < (uint32_t)lane && !canon_less(kc, c))) ? 1u : 0u;
+        }
+        uint32_t pv = 0;
+        if (PAY && (uint32_t)lane < L) pv = S.pay[e];
+        if ((uint32_t)lane < L) {
+            S.keys[s0 + rank] = k;
+            if (PAY) S.pay[s0 + rank] = pv;
+        }
+    }
+    __syncthreads();
+    const bool lng = S.long_run != 0u;
+    for (uint32_t i = threadIdx.x; i < nruns; i += BT) list[i] = 0u;  // the ranking tables start at zero
+    __syncthreads();
+    return lng;
+}
 
 // Waves per SIMD that the register budget must allow for a finish class:
 // as many blocks as fit a CU by LDS (160 KiB), at most 4 waves (a higher
@@ -1189,7 +1336,6 @@ void k_finish(Work w, int cls) {
     if (ctl->error | ctl->overflow) return;
     const uint32_t nfin = min(ctl->fin_ctr[cls], w.max_fin[cls]);
     const int wv = threadIdx.x / WAVE, lane = lane_id();
-    const uint32_t ebase = (uint32_t)wv * ITEMS * WAVE + (uint32_t)lane;
     for (int i = threadIdx.x; i < NW * R; i += BT) (&S.wh[0][0])[i] = 0u;
     for (int i = threadIdx.x; i < NW * 2 * R; i += BT) (&S.tbl[0][0])[i] = 0u;
     __syncthreads();
@@ -1239,62 +1385,22 @@ void k_finish(Work w, int cls) {
             diff.hi = ah ^ oh;
             diff.lo = al ^ ol;
         }
-        int hib = last_set_below(diff, bitpos, NB);
-        if (hib < bitpos && parity == 0u) {
+        const int lb = last_set_below(diff, bitpos, NB);  // least significant varying bit
+        if (lb < bitpos && parity == 0u) {
             // nothing varies and the keys already sit in A: nothing to write
             __syncthreads();
             continue;
         }
-        // least-significant window first; the order lives in S between passes
-        while (hib >= bitpos) {
-            const int lo = max(bitpos, hib - KL + 1);
-            const int wbits = hib - lo + 1;
-            V key[ITEMS];
-            uint32_t dg[ITEMS], rnk[ITEMS];
-#pragma unroll
-            for (int j = 0; j < ITEMS; ++j) {
-                const uint32_t e = ebase + j * WAVE;
-                key[j] = (e < len) ? S.keys[e] : KT::zero();
-                dg[j] = KT::digit(key[j], lo, wbits);
-            }
-            wave_rank<R, RANK_GROUP, ITEMS, false>(dg, ebase, len, &S.tbl[wv][0], &S.wh[wv][0], rnk);
-            uint32_t pay[ITEMS];
-#pragma unroll
-            for (int j = 0; j < ITEMS; ++j) {
-                const uint32_t e = ebase + j * WAVE;
-                if (PAY) pay[j] = (e < len) ? S.pay[e] : 0u;
-            }
-            __syncthreads();
-            uint32_t tcnt = 0;
-            if (threadIdx.x < R) {
-#pragma unroll
-                for (int q = 0; q < NW; ++q) tcnt += S.wh[q][threadIdx.x];
-            }
-            uint32_t tot;
-            uint32_t acc = block_excl_scan<BT>(tcnt, S.tmp, &tot);  // every thread: it holds barriers
-            if (threadIdx.x < R) {
-#pragma unroll
-                for (int q = 0; q < NW; ++q) {
-                    const uint32_t x = S.wh[q][threadIdx.x];
-                    S.wh[q][threadIdx.x] = acc;
-                    acc += x;
-                }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int j = 0; j < ITEMS; ++j) {
-                const uint32_t e = ebase + j * WAVE;
-                if (e < len) {
-                    const uint32_t pos = S.wh[wv][dg[j]] + rnk[j];
-                    S.keys[pos] = key[j];
-                    if (PAY) S.pay[pos] = pay[j];
-                }
-            }
-            __syncthreads();
-            // each wave clears its own counters: only it touches them before
-            // the next barrier
-            for (int i = lane; i < R; i += WAVE) S.wh[wv][i] = 0u;
-            hib = last_set_below(diff, bitpos, lo);
+        if (lb >= bitpos) {
+            // sort by the two leading 8-bit windows that start at varying bits;
+            // keys still tied on them are ordered by fix_runs, or, if a tied
+            // run is long, by passes over every varying bit
+            const int fb = first_set_from(diff, bitpos, NB);
+            const int f2 = first_set_from(diff, min(fb + 8, NB), NB);
+            const int pe = (f2 >= NB) ? lb : min(lb, f2 + 7);
+            lds_passes<KB, BT, ITEMS, PAY>(S, diff, bitpos, pe, len);
+            if (pe < lb && fix_runs<KB, BT, ITEMS, PAY>(S, pe, len))
+                lds_passes<KB, BT, ITEMS, PAY>(S, diff, bitpos, lb, len);
         }
         fin_store_keys<KB, BT>(w.keys[0], fe.begin, (size_t)fe.begin + len, S.keys);
         if constexpr (PAY) fin_store_pay<BT>(w.pay[0], fe.begin, (size_t)fe.begin + len, S.pay);

@@ -163,3 +163,32 @@ def test_finish_class_boundaries(kb):
     rk, rp = oracle.sort_segmented(keys, off, iota(n))
     assert np.array_equal(gk, rk)
     assert np.array_equal(gp, rp)
+
+
+@pytest.mark.parametrize("runlen", [1, 2, 63, 64, 65, 200])
+def test_tied_runs_after_leading_bits(runlen):
+    """The LDS finish sorts by the leading 16 varying bits and then orders
+    each run of keys tied on them: runs of up to 64 keys by ranking inside
+    one wave, longer ones by passes over every varying bit.  Segments whose
+    keys share their leading bits in runs of a chosen length, the rest random,
+    with ties in the full key as well."""
+    rng = np.random.default_rng(runlen)
+    lens = [int(x) for x in rng.integers(100, 5000, 40)]
+    off = np.zeros(len(lens) + 1, dtype=np.uint32)
+    off[1:] = np.cumsum(lens)
+    n = int(off[-1])
+    groups = max(1, n // runlen)
+    lead = rng.integers(0, 1 << 16, groups, dtype=np.uint64)[rng.integers(0, groups, n)]
+    low = rng.integers(0, 1 << 20, n, dtype=np.uint64)
+    low[rng.random(n) < 0.2] = 7                           # full-key ties too
+    keys = ((lead << np.uint64(48)) | low).astype(np.uint64)
+    print("tied runs len=%d n=%d" % (runlen, n), flush=True)
+    gk, gp = gpu_sort_segmented(keys, off, iota(n))
+    rk, rp = oracle.sort_segmented(keys, off, iota(n))
+    assert np.array_equal(gk, rk)
+    assert np.array_equal(gp, rp)
+    k32 = (lead.astype(np.uint32) << np.uint32(16)) | (low & np.uint64(0xFFFF)).astype(np.uint32)
+    gk, gp = gpu_sort_segmented(k32, off, iota(n))
+    rk, rp = oracle.sort_segmented(k32, off, iota(n))
+    assert np.array_equal(gk, rk)
+    assert np.array_equal(gp, rp)
