@@ -46,22 +46,34 @@ constexpr int HIST_BT = 1024;
 
 // LDS-finish classes per key width: (threads per block, keys per thread);
 // capacities 1024, 3072, 5120, 8192 keys (16-byte keys: 1024, 2048, 3072,
-// 5120).  Small classes use 256-thread blocks (a short segment leaves most of
-// a big block idle), the large ones 512.
+// 5120).  The finish is bound by LDS work: 256-thread blocks let several
+// independent blocks share a CU, so one block's loads and stores overlap
+// another's LDS passes.  Where even a 256-thread block is alone on its CU
+// (the largest class of 8- and 16-byte keys), 512 threads keep more waves.
 template <int KB>
-struct FinShape {
-    static constexpr int bt[NCLASS] = {256, 256, 512, 512};
-    static constexpr int items[NCLASS] = {4, 12, 10, 16};
+struct FinShape;
+template <>
+struct FinShape<4> {
+    static constexpr int bt[NCLASS] = {256, 256, 256, 256};
+    static constexpr int items[NCLASS] = {4, 12, 20, 32};
+};
+template <>
+struct FinShape<8> {
+    static constexpr int bt[NCLASS] = {256, 256, 256, 512};
+    static constexpr int items[NCLASS] = {4, 12, 20, 16};
 };
 template <>
 struct FinShape<16> {
-    static constexpr int bt[NCLASS] = {256, 256, 512, 512};
-    static constexpr int items[NCLASS] = {4, 8, 6, 10};
+    static constexpr int bt[NCLASS] = {256, 256, 256, 512};
+    static constexpr int items[NCLASS] = {4, 8, 12, 10};
 };
 
 uint32_t fin_cap(uint32_t kb, int c) {
-    return kb == 16 ? (uint32_t)(FinShape<16>::bt[c] * FinShape<16>::items[c])
-                    : (uint32_t)(FinShape<4>::bt[c] * FinShape<4>::items[c]);
+    switch (kb) {
+        case 4: return (uint32_t)(FinShape<4>::bt[c] * FinShape<4>::items[c]);
+        case 8: return (uint32_t)(FinShape<8>::bt[c] * FinShape<8>::items[c]);
+        default: return (uint32_t)(FinShape<16>::bt[c] * FinShape<16>::items[c]);
+    }
 }
 
 // Scatter tiles: (threads per block, keys per thread) per tile size.

@@ -1252,9 +1252,11 @@ __device__ bool fix_runs(FinishLds<KB, BT, ITEMS, PAY> &S, int pe, uint32_t len)
     using V = typename KT::V;
     constexpr int NW = BT / WAVE;
     constexpr int CAP = BT * ITEMS;
-    constexpr uint32_t LIST = NW * 2 * (1u << 8);
-    static_assert(LIST >= CAP / 2, "run list must hold every possible run start");
-    uint32_t *list = &S.tbl[0][0];
+    // run starts as 16-bit positions in the (zero) lane-mask table
+    typedef uint16_t __attribute__((may_alias)) pos16_t;
+    constexpr uint32_t LIST = NW * 2 * (1u << 8) * 2;
+    static_assert(LIST >= CAP / 2 && CAP <= 65536, "run list must hold every possible run start");
+    pos16_t *list = reinterpret_cast<pos16_t *>(&S.tbl[0][0]);
     const int wv = threadIdx.x / WAVE, lane = lane_id();
     Canon pm;
     pm.hi = pe >= 63 ? ~0ull : ~(~0ull >> (pe + 1));
@@ -1272,7 +1274,7 @@ __device__ bool fix_runs(FinishLds<KB, BT, ITEMS, PAY> &S, int pe, uint32_t len)
     uint32_t nruns;
     uint32_t at = block_excl_scan<BT>(cnt, S.tmp, &nruns);  // every thread: it holds barriers
     for (uint32_t p = threadIdx.x; p < len; p += BT)
-        if (is_start(p)) list[at++] = p;
+        if (is_start(p)) list[at++] = (uint16_t)p;
     __syncthreads();
     for (uint32_t r = wv; r < nruns; r += NW) {
         const uint32_t s0 = list[r];
@@ -1305,7 +1307,8 @@ __device__ bool fix_runs(FinishLds<KB, BT, ITEMS, PAY> &S, int pe, uint32_t len)
     }
     __syncthreads();
     const bool lng = S.long_run != 0u;
-    for (uint32_t i = threadIdx.x; i < nruns; i += BT) list[i] = 0u;  // the ranking tables start at zero
+    // the ranking tables start at zero
+    for (uint32_t i = threadIdx.x; i < (nruns + 1u) / 2u; i += BT) (&S.tbl[0][0])[i] = 0u;
     __syncthreads();
     return lng;
 }
