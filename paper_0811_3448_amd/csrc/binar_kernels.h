@@ -895,8 +895,11 @@ __device__ __forceinline__ void scatter_tile(const Work &w, int L, ScatterLds<KB
                 S.ckeys[d][g - S.wlim[d]] = k;
                 if (PAY) S.cpay[d][g - S.wlim[d]] = S.pay[p];
             } else if (g < w.n_total) {
-                KT::store(dst, g, k);
-                if (PAY) pdst[g] = S.pay[p];
+                // whole bursts from this tile: streaming stores (the partial
+                // bursts completed from the carry above stay ordinary, so the
+                // cache merges their two halves)
+                KT::store_nt(dst, g, k);
+                if (PAY) __builtin_nontemporal_store(S.pay[p], pdst + g);
             } else {
                 atomicOr(&ctl->error, ERR_INTERNAL);
             }

@@ -40,6 +40,10 @@ struct KeyT<4> {
     __device__ static __forceinline__ void store(void *p, size_t i, V v) {
         reinterpret_cast<uint32_t *>(p)[i] = v;
     }
+    // streaming store: the data is not read again soon, keep it out of the caches
+    __device__ static __forceinline__ void store_nt(void *p, size_t i, V v) {
+        __builtin_nontemporal_store(v, reinterpret_cast<uint32_t *>(p) + i);
+    }
     // bits [pos, pos + w) counted from the MSB, 1 <= w <= 8, pos + w <= 32
     __device__ static __forceinline__ uint32_t digit(V v, int pos, int w) {
         return (v >> (32 - pos - w)) & ((1u << w) - 1u);
@@ -60,6 +64,9 @@ struct KeyT<8> {
     }
     __device__ static __forceinline__ void store(void *p, size_t i, V v) {
         reinterpret_cast<uint64_t *>(p)[i] = v;
+    }
+    __device__ static __forceinline__ void store_nt(void *p, size_t i, V v) {
+        __builtin_nontemporal_store(v, reinterpret_cast<uint64_t *>(p) + i);
     }
     __device__ static __forceinline__ uint32_t digit(V v, int pos, int w) {
         return (uint32_t)(v >> (64 - pos - w)) & ((1u << w) - 1u);
@@ -84,6 +91,13 @@ struct KeyT<16> {
         raw.x = bswap64(v.hi);
         raw.y = bswap64(v.lo);
         reinterpret_cast<ulonglong2 *>(p)[i] = raw;
+    }
+    __device__ static __forceinline__ void store_nt(void *p, size_t i, V v) {
+        typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+        u64x2 raw;
+        raw.x = bswap64(v.hi);
+        raw.y = bswap64(v.lo);
+        __builtin_nontemporal_store(raw, reinterpret_cast<u64x2 *>(p) + i);
     }
     __device__ static __forceinline__ uint32_t digit(V v, int pos, int w) {
         const uint32_t m = (1u << w) - 1u;
