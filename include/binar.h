@@ -83,15 +83,34 @@ extern "C" {
  *   key_bits   : sort by the leading key_bits bits of each key only (1 ..
  *                8 * key_bytes; 0 = all): keys equal in those bits keep
  *                their input order.  This is the state the method reaches
- *                after partitioning on the first key_bits bits. */
+ *                after partitioning on the first key_bits bits.
+ *   key_kind   : how the bits of a 4- or 8-byte key are ordered (the paper
+ *                claims the method for any data type whose encoding orders
+ *                it; section "The Other Universal Property"):
+ *                BINAR_KEY_UNSIGNED (0) unsigned integers;
+ *                BINAR_KEY_SIGNED   (1) two's-complement integers;
+ *                BINAR_KEY_FLOAT    (2) IEEE-754 binary32 / binary64 in the
+ *                  standard's total order: -NaN < -inf < negative values <
+ *                  -0 < +0 < positive values < +inf < +NaN (NaNs of one
+ *                  sign ordered by payload bits; -0 before +0).
+ *                The sort reads each key through an order-preserving
+ *                unsigned view (flip the sign bit of signed and non-negative
+ *                float keys, every bit of negative float keys) and writes the
+ *                caller's bits back unchanged.  16-byte keys take 0 only; a
+ *                call's key_kind is never taken from the defaults. */
 typedef struct binar_params {
     uint32_t digit_bits;
     uint32_t tile_keys;
     uint32_t finish_max;
     uint32_t offsets;
     uint32_t key_bits;
-    uint32_t reserved[3];
+    uint32_t key_kind;
+    uint32_t reserved[2];
 } binar_params;
+
+#define BINAR_KEY_UNSIGNED 0u
+#define BINAR_KEY_SIGNED 1u
+#define BINAR_KEY_FLOAT 2u
 
 /* Counters of the last call that used a workspace (exact integers).
  *   moved[j]       keys scattered by global pass j (pass-through and

@@ -9,6 +9,9 @@ C ABI.  The binding only marshals arguments: torch tensors supply device
 memory and streams, every step of the sort runs in the library's kernels.
 """
 from .binar import (  # noqa: F401
+    KEY_FLOAT,
+    KEY_SIGNED,
+    KEY_UNSIGNED,
     BinarError,
     Params,
     Plan,

@@ -19,7 +19,8 @@ MAX_KEYS = (1 << 30) - 1
 class _Params(ctypes.Structure):
     _fields_ = [("digit_bits", ctypes.c_uint32), ("tile_keys", ctypes.c_uint32),
                 ("finish_max", ctypes.c_uint32), ("offsets", ctypes.c_uint32),
-                ("key_bits", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 3)]
+                ("key_bits", ctypes.c_uint32), ("key_kind", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 2)]
 
 
 class _Stats(ctypes.Structure):
@@ -97,19 +98,23 @@ def _check(rc: int) -> None:
 
 
 OFFSETS_CHUNKED, OFFSETS_LOOKBACK = 1, 2
+KEY_UNSIGNED, KEY_SIGNED, KEY_FLOAT = 0, 1, 2
 
 
 @dataclass
 class Params:
-    """Tuning knobs (0 = library default); see binar_params in binar.h."""
+    """Tuning knobs (0 = library default) and the key kind; see binar_params
+    in binar.h."""
     digit_bits: int = 0
     tile_keys: int = 0
     finish_max: int = 0
     offsets: int = 0
     key_bits: int = 0
+    key_kind: int = 0
 
     def c(self):
-        return _Params(self.digit_bits, self.tile_keys, self.finish_max, self.offsets, self.key_bits)
+        return _Params(self.digit_bits, self.tile_keys, self.finish_max, self.offsets, self.key_bits,
+                       self.key_kind)
 
 
 def key_bytes_of(keys) -> int:
@@ -131,6 +136,25 @@ def _stream_ptr(stream):
 
 def _dev_ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def key_kind_of(keys, params: "Params | None", key_kind: int | None) -> "Params | None":
+    """Params carrying the key kind: the explicit key_kind, else the one in
+    params, else KEY_FLOAT for floating-point tensors (their bits read as
+    unsigned integers would not be in numeric order).  Integer tensors are
+    read as unsigned unless told otherwise (torch has no uint32 tensors, so
+    int32 storage often holds unsigned keys)."""
+    import torch
+    if key_kind is None:
+        if params is not None and params.key_kind:
+            return params
+        if keys.dtype in (torch.float32, torch.float64):
+            key_kind = KEY_FLOAT
+        else:
+            return params
+    p = Params() if params is None else Params(**vars(params))
+    p.key_kind = key_kind
+    return p
 
 
 def _check_tensors(keys, payload):
@@ -162,10 +186,12 @@ def workspace_bytes(key_bytes: int, n: int, has_payload: bool, num_segments: int
 
 
 def sort(keys, payload=None, stream=None, workspace: Workspace | None = None,
-         params: Params | None = None):
+         params: Params | None = None, key_kind: int | None = None):
     """Sort keys (and payload) in place on `stream` (default: torch's current
-    stream).  Returns keys.  Asynchronous like any torch op."""
+    stream).  Returns keys.  Asynchronous like any torch op.  key_kind: see
+    key_kind_of."""
     _check_tensors(keys, payload)
+    params = key_kind_of(keys, params, key_kind)
     kb = key_bytes_of(keys)
     n = keys.shape[0]
     ws = (None, 0) if workspace is None else (workspace.ptr, workspace.nbytes)
@@ -176,10 +202,11 @@ def sort(keys, payload=None, stream=None, workspace: Workspace | None = None,
 
 
 def sort_segmented(keys, seg_offsets, payload=None, stream=None, workspace: Workspace | None = None,
-                   params: Params | None = None):
+                   params: Params | None = None, key_kind: int | None = None):
     """Sort every segment [off[s], off[s+1]) of keys independently, in place.
     seg_offsets: device int32/uint32 tensor of S + 1 nondecreasing offsets."""
     _check_tensors(keys, payload)
+    params = key_kind_of(keys, params, key_kind)
     if not seg_offsets.is_cuda or seg_offsets.element_size() != 4 or seg_offsets.dim() != 1 \
             or not seg_offsets.is_contiguous():
         raise ValueError("seg_offsets must be a contiguous 1-D 4-byte device tensor")
@@ -286,7 +313,7 @@ def resolve_params(key_bytes: int, has_payload: bool, params: Params | None = No
     p = _Params()
     _check(lib.binar_resolve_params(key_bytes, 1 if has_payload else 0,
                                     None if params is None else ctypes.byref(params.c()), ctypes.byref(p)))
-    return Params(p.digit_bits, p.tile_keys, p.finish_max, p.offsets, p.key_bits)
+    return Params(p.digit_bits, p.tile_keys, p.finish_max, p.offsets, p.key_bits, p.key_kind)
 
 
 def set_default_params(key_bytes: int, has_payload: bool, params: Params) -> None:

@@ -93,7 +93,7 @@ struct ScatterShape<8192> {
 };
 
 struct Resolved {
-    uint32_t kb, k, tile, T, nbits;
+    uint32_t kb, k, tile, T, nbits, kind;
     bool pay;
     bool lookback;
 };
@@ -133,7 +133,11 @@ int resolve_over(uint32_t kb, bool pay, binar_params d, const binar_params *p, R
     if (d.tile_keys == 2048 && d.digit_bits > 4 && d.digit_bits < 8) return BINAR_EINVAL;
     const uint32_t nbits = (p && p->key_bits) ? p->key_bits : 8u * kb;
     if (nbits > 8u * kb) return BINAR_EINVAL;
+    // the key kind belongs to the call, never to the defaults
+    const uint32_t kind = p ? p->key_kind : 0u;
+    if (kind > KIND_FLOAT || (kind != KIND_UNSIGNED && kb == 16)) return BINAR_EINVAL;
     r->nbits = nbits;
+    r->kind = kind;
     r->kb = kb;
     r->k = d.digit_bits;
     r->tile = d.tile_keys;
@@ -281,6 +285,7 @@ Work make_work(const Layout &L, const Resolved &r, char *ws, void *keys, uint32_
     w.finish_max = r.T;
     w.tile_keys = r.tile;
     w.nbits = r.nbits;
+    w.kind = r.kind;
     w.n_total = n_total;
     w.keys[0] = keys;
     w.keys[1] = ws + L.keys_b;
@@ -711,6 +716,7 @@ int binar_resolve_params(uint32_t key_bytes, int has_payload, const binar_params
     out->finish_max = r.T;
     out->offsets = r.lookback ? 2u : 1u;
     out->key_bits = r.nbits;
+    out->key_kind = r.kind;
     return BINAR_OK;
 }
 
@@ -722,6 +728,7 @@ int binar_set_default_params(uint32_t key_bytes, int has_payload, const binar_pa
     if (!valid_kb(key_bytes) || !p) return BINAR_EINVAL;
     binar_params d = *p;
     d.key_bits = 0;  // the defaults always sort whole keys
+    d.key_kind = 0;  // and say nothing about how keys are read
     Resolved r;
     if (int rc = resolve_over(key_bytes, has_payload != 0, d, nullptr, &r)) return rc;
     std::lock_guard<std::mutex> lk(g_mu);

@@ -114,6 +114,7 @@ struct Work {
     uint32_t n_total;              // keys in A and B: every index written is below it
     uint32_t chunk_grid;           // blocks of k_hist / k_scatter: fixes the pieces
     uint32_t nbits;                // leading key bits to sort by (the key width unless limited)
+    uint32_t kind;                 // KIND_*: how key bits are ordered; loads apply enc, stores dec
     void *keys[2];                 // A, B
     uint32_t *pay[2];              // A, B (NULL without payload)
 };
@@ -365,6 +366,18 @@ __device__ __forceinline__ void load_vec(const void *p, size_t i, typename KeyT<
     }
 }
 
+// Key i of a buffer in the sorting view (enc), and back.
+template <int KB>
+__device__ __forceinline__ typename KeyT<KB>::V ld_key(const void *p, size_t i, uint32_t kind) {
+    const typename KeyT<KB>::V v = KeyT<KB>::load(p, i);
+    return kind ? KeyT<KB>::enc(v, kind) : v;
+}
+
+template <int KB>
+__device__ __forceinline__ typename KeyT<KB>::V raw_key(typename KeyT<KB>::V v, uint32_t kind) {
+    return kind ? KeyT<KB>::dec(v, kind) : v;
+}
+
 // ------------------------------------------------------------------- k_hist
 // Digit counts (bits [bitpos, bitpos + w) of each key) and AND/OR of every
 // live segment of list L.  The tiles of the list are cut into gridDim.x
@@ -410,6 +423,7 @@ __global__ __launch_bounds__(BT) void k_hist(Work w, int L) {
         const uint32_t te = min(t1, seg_tile_end(w.list[L], slot, nslots, ntiles));
         const uint32_t bitpos = seg.info & 0xFFu, parity = (seg.info >> 8) & 1u;
         const int wbits = min(K, (int)w.nbits - (int)bitpos);
+        const uint32_t kind = w.kind;
         const void *src = w.keys[parity];
         const size_t g0 = (size_t)seg.begin + (size_t)(t - seg.tile_start) * w.tile_keys;
         const size_t g1 = (size_t)seg.begin + min((size_t)seg.len, (size_t)(te - seg.tile_start) * w.tile_keys);
@@ -420,13 +434,13 @@ __global__ __launch_bounds__(BT) void k_hist(Work w, int L) {
         const size_t b0 = min(g1, g0 + ((mis + VN - (g0 % VN)) % VN));
         const size_t b1 = b0 + (g1 - b0) / VN * VN;
         for (size_t i = g0 + threadIdx.x; i < b0; i += BT) {
-            const V v = KT::load(src, i);
+            const V v = ld_key<KB>(src, i, kind);
             atomicAdd(&s_h[wv][KT::digit(v, bitpos, wbits)], 1u);
             a = KT::vand(a, v);
             o = KT::vor(o, v);
         }
         for (size_t i = b1 + threadIdx.x; i < g1; i += BT) {
-            const V v = KT::load(src, i);
+            const V v = ld_key<KB>(src, i, kind);
             atomicAdd(&s_h[wv][KT::digit(v, bitpos, wbits)], 1u);
             a = KT::vand(a, v);
             o = KT::vor(o, v);
@@ -444,6 +458,7 @@ __global__ __launch_bounds__(BT) void k_hist(Work w, int L) {
                 if (x < b1) {
 #pragma unroll
                     for (int q = 0; q < VN; ++q) {
+                        if (kind) v[u][q] = KT::enc(v[u][q], kind);
                         atomicAdd(&s_h[wv][KT::digit(v[u][q], bitpos, wbits)], 1u);
                         a = KT::vand(a, v[u][q]);
                         o = KT::vor(o, v[u][q]);
@@ -733,7 +748,9 @@ struct ScatterLds {
     uint32_t tile, slot;
 };
 
-// Keys (and payloads) of tile t of `seg` into registers, wave-striped.
+// Keys (and payloads) of tile t of `seg` into registers, wave-striped, as
+// stored (the sorting view is taken when the tile is processed, so that the
+// loads of a prefetched tile stay in flight).
 template <int KB, int BT, int ITEMS, bool PAY>
 __device__ __forceinline__ void load_tile(const Work &w, const SegEntry &seg, uint32_t t,
                                           typename KeyT<KB>::V (&key)[ITEMS], uint32_t (&pay)[ITEMS]) {
@@ -767,7 +784,7 @@ __device__ __forceinline__ void load_tile(const Work &w, const SegEntry &seg, ui
 template <int KB, int K, int BT, int ITEMS, bool PAY, bool LOOKBACK, bool FULL>
 __device__ __forceinline__ void scatter_tile(const Work &w, int L, ScatterLds<KB, K, BT, ITEMS, PAY, LOOKBACK> &S,
                                              const SegEntry &seg, uint32_t t, uint32_t slot,
-                                             const typename KeyT<KB>::V (&key)[ITEMS], const uint32_t (&pay)[ITEMS]) {
+                                             typename KeyT<KB>::V (&key)[ITEMS], const uint32_t (&pay)[ITEMS]) {
     using KT = KeyT<KB>;
     using V = typename KT::V;
     constexpr int R = 1 << K;
@@ -786,6 +803,11 @@ __device__ __forceinline__ void scatter_tile(const Work &w, int L, ScatterLds<KB
     uint32_t dg[ITEMS];
     uint32_t rnk[ITEMS];
     const uint32_t ebase = (uint32_t)wv * ITEMS * WAVE + (uint32_t)lane;
+    // the tile's keys, loaded as stored, into the sorting view (in place)
+    if (w.kind) {
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) key[j] = KT::enc(key[j], w.kind);
+    }
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) dg[j] = KT::digit(key[j], bitpos, wbits);
     wave_rank<R, RANK_GROUP, ITEMS, FULL>(dg, ebase, tlen, &S.tbl[wv][0], &S.wh[wv][0], rnk);
@@ -871,7 +893,7 @@ __device__ __forceinline__ void scatter_tile(const Work &w, int L, ScatterLds<KB
             if ((uint32_t)k < S.ccw[d]) {
                 const uint32_t g = S.clo[d] + k;
                 if (g < w.n_total) {
-                    KT::store(dst, g, S.ckeys[d][k]);
+                    KT::store(dst, g, raw_key<KB>(S.ckeys[d][k], w.kind));
                     if (PAY) pdst[g] = S.cpay[d][k];
                 } else {
                     atomicOr(&ctl->error, ERR_INTERNAL);
@@ -898,7 +920,7 @@ __device__ __forceinline__ void scatter_tile(const Work &w, int L, ScatterLds<KB
                 // whole bursts from this tile: streaming stores (the partial
                 // bursts completed from the carry above stay ordinary, so the
                 // cache merges their two halves)
-                KT::store_nt(dst, g, k);
+                KT::store_nt(dst, g, raw_key<KB>(k, w.kind));
                 if (PAY) __builtin_nontemporal_store(S.pay[p], pdst + g);
             } else {
                 atomicOr(&ctl->error, ERR_INTERNAL);
@@ -923,7 +945,7 @@ __device__ __forceinline__ void flush_carry(const Work &w, ScatterLds<KB, K, BT,
         if ((uint32_t)k < S.cc[d]) {
             const uint32_t g = S.run[d] - S.cc[d] + k;
             if (g < w.n_total) {
-                KT::store(dst, g, S.ckeys[d][k]);
+                KT::store(dst, g, raw_key<KB>(S.ckeys[d][k], w.kind));
                 if (PAY) pdst[g] = S.cpay[d][k];
             } else {
                 atomicOr(&w.ctl->error, ERR_INTERNAL);
@@ -1054,7 +1076,7 @@ __device__ __forceinline__ void aligned_body(const void *base, size_t g0, size_t
 
 template <int KB, int NV, int BT>
 __device__ __forceinline__ void fin_load_keys(const void *src, size_t g0, size_t g1, typename KeyT<KB>::V *lds,
-                                              typename KeyT<KB>::V &a, typename KeyT<KB>::V &o) {
+                                              typename KeyT<KB>::V &a, typename KeyT<KB>::V &o, uint32_t kind) {
     using KT = KeyT<KB>;
     using V = typename KT::V;
     constexpr int VN = Vec<KB>::N;
@@ -1067,13 +1089,13 @@ __device__ __forceinline__ void fin_load_keys(const void *src, size_t g0, size_t
         if (x < b1) load_vec<KB>(src, x, v[u]);
     }
     for (size_t i = g0 + threadIdx.x; i < b0; i += BT) {
-        const V k = KT::load(src, i);
+        const V k = ld_key<KB>(src, i, kind);
         lds[i - g0] = k;
         a = KT::vand(a, k);
         o = KT::vor(o, k);
     }
     for (size_t i = b1 + threadIdx.x; i < g1; i += BT) {
-        const V k = KT::load(src, i);
+        const V k = ld_key<KB>(src, i, kind);
         lds[i - g0] = k;
         a = KT::vand(a, k);
         o = KT::vor(o, k);
@@ -1084,6 +1106,7 @@ __device__ __forceinline__ void fin_load_keys(const void *src, size_t g0, size_t
         if (x < b1) {
 #pragma unroll
             for (int q = 0; q < VN; ++q) {
+                if (kind) v[u][q] = KT::enc(v[u][q], kind);
                 lds[x - g0 + q] = v[u][q];
                 a = KT::vand(a, v[u][q]);
                 o = KT::vor(o, v[u][q]);
@@ -1118,24 +1141,27 @@ __device__ __forceinline__ void fin_load_pay(const uint32_t *src, size_t g0, siz
 }
 
 template <int KB, int BT>
-__device__ __forceinline__ void fin_store_keys(void *dst, size_t g0, size_t g1, const typename KeyT<KB>::V *lds) {
+__device__ __forceinline__ void fin_store_keys(void *dst, size_t g0, size_t g1, const typename KeyT<KB>::V *lds,
+                                               uint32_t kind) {
     using KT = KeyT<KB>;
     constexpr int VN = Vec<KB>::N;
     size_t b0, b1;
     aligned_body<VN, KB>(dst, g0, g1, b0, b1);
-    for (size_t i = g0 + threadIdx.x; i < b0; i += BT) KT::store(dst, i, lds[i - g0]);
-    for (size_t i = b1 + threadIdx.x; i < g1; i += BT) KT::store(dst, i, lds[i - g0]);
+    for (size_t i = g0 + threadIdx.x; i < b0; i += BT) KT::store(dst, i, raw_key<KB>(lds[i - g0], kind));
+    for (size_t i = b1 + threadIdx.x; i < g1; i += BT) KT::store(dst, i, raw_key<KB>(lds[i - g0], kind));
     for (size_t x = b0 + (size_t)threadIdx.x * VN; x < b1; x += (size_t)BT * VN) {
         const typename KT::V *s = lds + (x - g0);
         if constexpr (KB == 4) {
-            *reinterpret_cast<uint4 *>(reinterpret_cast<uint32_t *>(dst) + x) = make_uint4(s[0], s[1], s[2], s[3]);
+            *reinterpret_cast<uint4 *>(reinterpret_cast<uint32_t *>(dst) + x) =
+                make_uint4(raw_key<KB>(s[0], kind), raw_key<KB>(s[1], kind), raw_key<KB>(s[2], kind),
+                           raw_key<KB>(s[3], kind));
         } else if constexpr (KB == 8) {
             ulonglong2 r;
-            r.x = s[0];
-            r.y = s[1];
+            r.x = raw_key<KB>(s[0], kind);
+            r.y = raw_key<KB>(s[1], kind);
             *reinterpret_cast<ulonglong2 *>(reinterpret_cast<uint64_t *>(dst) + x) = r;
         } else {
-            KT::store(dst, x, s[0]);
+            KT::store(dst, x, raw_key<KB>(s[0], kind));
         }
     }
 }
@@ -1361,7 +1387,7 @@ void k_finish(Work w, int cls) {
         // load into LDS in input order, AND/OR on the way
         V a = KT::ones(), o = KT::zero();
         fin_load_keys<KB, (CAP + Vec<KB>::N * BT - 1) / (Vec<KB>::N * BT), BT>(
-            w.keys[parity], fe.begin, (size_t)fe.begin + len, S.keys, a, o);
+            w.keys[parity], fe.begin, (size_t)fe.begin + len, S.keys, a, o, w.kind);
         if constexpr (PAY) fin_load_pay<(CAP + 4 * BT - 1) / (4 * BT), BT>(w.pay[parity], fe.begin, (size_t)fe.begin + len, S.pay);
         Canon ca = KT::canon(a), co = KT::canon(o);
 #pragma unroll
@@ -1408,7 +1434,7 @@ void k_finish(Work w, int cls) {
             if (pe < lb && fix_runs<KB, BT, ITEMS, PAY>(S, pe, len))
                 lds_passes<KB, BT, ITEMS, PAY>(S, diff, bitpos, lb, len);
         }
-        fin_store_keys<KB, BT>(w.keys[0], fe.begin, (size_t)fe.begin + len, S.keys);
+        fin_store_keys<KB, BT>(w.keys[0], fe.begin, (size_t)fe.begin + len, S.keys, w.kind);
         if constexpr (PAY) fin_store_pay<BT>(w.pay[0], fe.begin, (size_t)fe.begin + len, S.pay);
         __syncthreads();
     }

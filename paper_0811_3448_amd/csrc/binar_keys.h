@@ -27,6 +27,13 @@ struct Canon {
 
 __device__ __forceinline__ uint64_t bswap64(uint64_t x) { return __builtin_bswap64(x); }
 
+// How the bits of a key are ordered: as an unsigned integer (the paper's
+// bit-string order), as a two's-complement integer, or as an IEEE-754 value
+// in the standard's total order (-NaN < -inf < ... < -0 < +0 < ... < +inf <
+// +NaN).  The kernels sort the unsigned view enc(v), which flips the sign bit
+// of signed and non-negative float keys and every bit of negative float keys.
+constexpr uint32_t KIND_UNSIGNED = 0, KIND_SIGNED = 1, KIND_FLOAT = 2;
+
 template <int KB>
 struct KeyT;
 
@@ -53,6 +60,18 @@ struct KeyT<4> {
     __device__ static __forceinline__ V vand(V a, V b) { return a & b; }
     __device__ static __forceinline__ V vor(V a, V b) { return a | b; }
     __device__ static __forceinline__ Canon canon(V v) { return Canon{(uint64_t)v << 32, 0ull}; }
+    // the order-preserving unsigned view of a signed (KIND_SIGNED) or IEEE-754
+    // (KIND_FLOAT) key, and its inverse
+    __device__ static __forceinline__ V enc(V v, uint32_t kind) {
+        const V sb = 0x80000000u;
+        if (kind == KIND_SIGNED) return v ^ sb;
+        return v ^ ((V)((int32_t)v >> 31) | sb);
+    }
+    __device__ static __forceinline__ V dec(V e, uint32_t kind) {
+        const V sb = 0x80000000u;
+        if (kind == KIND_SIGNED) return e ^ sb;
+        return e ^ ((e & sb) ? sb : ~0u);
+    }
 };
 
 template <>
@@ -76,6 +95,16 @@ struct KeyT<8> {
     __device__ static __forceinline__ V vand(V a, V b) { return a & b; }
     __device__ static __forceinline__ V vor(V a, V b) { return a | b; }
     __device__ static __forceinline__ Canon canon(V v) { return Canon{v, 0ull}; }
+    __device__ static __forceinline__ V enc(V v, uint32_t kind) {
+        const V sb = 0x8000000000000000ull;
+        if (kind == KIND_SIGNED) return v ^ sb;
+        return v ^ ((V)((int64_t)v >> 63) | sb);
+    }
+    __device__ static __forceinline__ V dec(V e, uint32_t kind) {
+        const V sb = 0x8000000000000000ull;
+        if (kind == KIND_SIGNED) return e ^ sb;
+        return e ^ ((e & sb) ? sb : ~0ull);
+    }
 };
 
 template <>
@@ -111,6 +140,9 @@ struct KeyT<16> {
     __device__ static __forceinline__ V vand(V a, V b) { return U128{a.hi & b.hi, a.lo & b.lo}; }
     __device__ static __forceinline__ V vor(V a, V b) { return U128{a.hi | b.hi, a.lo | b.lo}; }
     __device__ static __forceinline__ Canon canon(V v) { return Canon{v.hi, v.lo}; }
+    // byte strings have no other view
+    __device__ static __forceinline__ V enc(V v, uint32_t) { return v; }
+    __device__ static __forceinline__ V dec(V v, uint32_t) { return v; }
 };
 
 // First bit index >= pos (MSB-first) set in the left-aligned word d, or

@@ -84,3 +84,15 @@ def test_workspace_bytes(lib):
     p = binar.default_params(4, True)
     assert p.digit_bits == 8 and p.tile_keys in (2048, 4096, 8192) and p.finish_max > 0
     assert binar.default_params(8, True).tile_keys in (2048, 4096)
+
+
+def test_key_kind_params(lib):
+    from paper_0811_3448_amd import KEY_FLOAT, KEY_SIGNED, BinarError, Params, default_params, resolve_params
+    for kb in (4, 8):
+        for kind in (0, KEY_SIGNED, KEY_FLOAT):
+            assert resolve_params(kb, True, Params(key_kind=kind)).key_kind == kind
+    with pytest.raises(BinarError):
+        resolve_params(16, True, Params(key_kind=KEY_SIGNED))       # byte strings have one order
+    with pytest.raises(BinarError):
+        resolve_params(4, True, Params(key_kind=3))
+    assert default_params(4, True).key_kind == 0                    # never part of the defaults

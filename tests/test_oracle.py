@@ -306,3 +306,84 @@ def test_appendix_exchange_sort_agrees_on_keys():
         out = binar_swap_sort(vals.tolist(), 12)
         k, _ = oracle.sort_bits(vals, 12)
         assert out == k.tolist()
+
+
+# ---------------------------------------------------------------- key kinds
+# The orders of signed and IEEE-754 keys (oracle.orders), pinned against
+# numpy's own comparisons and against hand-written special-value orders.
+
+def _f32_bits(x):
+    return np.asarray(x, dtype=np.float32).view(np.uint32)
+
+
+def _f64_bits(x):
+    return np.asarray(x, dtype=np.float64).view(np.uint64)
+
+
+@pytest.mark.parametrize("width", [32, 64])
+def test_kind_signed_matches_numpy(width):
+    from oracle import orders
+    rng = np.random.default_rng(width)
+    it = np.int32 if width == 32 else np.int64
+    ut = np.uint32 if width == 32 else np.uint64
+    info = np.iinfo(it)
+    v = rng.integers(info.min, info.max, 5000, dtype=it, endpoint=True)
+    v[:6] = [info.min, info.max, -1, 0, 1, info.min + 1]
+    v[6:400] = v[rng.integers(0, 6, 394)]                  # ties
+    keys = v.view(ut)
+    p = orders.stable_order(keys, orders.SIGNED)
+    assert np.array_equal(p, np.argsort(v, kind="stable"))
+
+
+@pytest.mark.parametrize("width", [32, 64])
+def test_kind_float_matches_numpy_without_zero_or_nan(width):
+    """numpy orders floats numerically (and keeps -0 == +0, NaN last), so
+    the comparison leaves out zeros and NaNs; they are pinned below."""
+    from oracle import orders
+    rng = np.random.default_rng(100 + width)
+    ft = np.float32 if width == 32 else np.float64
+    v = (rng.standard_normal(5000) * 10.0 ** rng.integers(-30, 30, 5000)).astype(ft)
+    v[:4] = [np.inf, -np.inf, np.finfo(ft).max, -np.finfo(ft).tiny / 4]  # infinities, max, a subnormal
+    v[4:300] = v[rng.integers(0, 4, 296)]
+    v[v == 0] = 1
+    bits = v.view(np.uint32 if width == 32 else np.uint64)
+    p = orders.stable_order(bits, orders.FLOAT)
+    assert np.array_equal(p, np.argsort(v, kind="stable"))
+
+
+def test_kind_float_special_values_order():
+    from oracle import orders
+    qnan = 0x7FC00000
+    vals = [0x7F800000 | 1, qnan, 0xFFC00000, 0xFF800001,  # +sNaN, +qNaN, -qNaN, -sNaN
+            0x7F800000, 0xFF800000,                          # +inf, -inf
+            0x80000000, 0x00000000,                          # -0, +0
+            0x00000001, 0x80000001,                          # +/- smallest subnormal
+            _f32_bits(1.0), _f32_bits(-1.0), _f32_bits(2.5), _f32_bits(-2.5)]
+    keys = np.array([int(x) for x in vals], dtype=np.uint32)
+    p = orders.stable_order(keys, orders.FLOAT)
+    expect = [0xFFC00000, 0xFF800001, 0xFF800000, _f32_bits(-2.5), _f32_bits(-1.0), 0x80000001,
+              0x80000000, 0x00000000, 0x00000001, _f32_bits(1.0), _f32_bits(2.5), 0x7F800000,
+              0x7F800000 | 1, qnan]
+    # total order: -qNaN (payload 0x400000) is below -sNaN (payload 1), and
+    # +sNaN below +qNaN
+    assert [int(x) for x in keys[p]] == [int(x) for x in expect]
+
+
+def test_kind_unsigned_matches_oracle():
+    from oracle import orders
+    keys = np.random.default_rng(5).integers(0, 1 << 32, 3000, dtype=np.uint64).astype(np.uint32)
+    keys[100:800] = keys[:700] & 0xFF
+    rk, rp = oracle.sort(keys, np.arange(3000, dtype=np.uint32))
+    ok, op = orders.sort(keys, np.arange(3000, dtype=np.uint32), orders.UNSIGNED)
+    assert np.array_equal(ok, rk) and np.array_equal(op, rp)
+
+
+def test_kind_planted_mistake_fails():
+    """A float order that forgets to reverse negative magnitudes must fail
+    the numpy pin (the check can catch a wrong formula)."""
+    rng = np.random.default_rng(7)
+    v = rng.standard_normal(200).astype(np.float32)
+    bits = v.view(np.uint32)
+    wrong = np.where(bits >> 31, -(bits & 0x7FFFFFFF).astype(np.int64), (bits & 0x7FFFFFFF).astype(np.int64))
+    wrong = np.where(bits >> 31, -wrong - 1, wrong)   # magnitude order kept for negatives: wrong
+    assert not np.array_equal(np.argsort(wrong, kind="stable"), np.argsort(v, kind="stable"))

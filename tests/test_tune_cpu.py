@@ -80,7 +80,7 @@ def test_install_sets_library_defaults(tmp_path):
     try:
         done = c.install()
         assert done == [(8, True, {"digit_bits": 6, "tile_keys": 4096, "finish_max": 5120, "offsets": 1,
-                                   "key_bits": 0})]
+                                   "key_bits": 0, "key_kind": 0})]
         p = default_params(8, True)
         assert (p.digit_bits, p.tile_keys, p.finish_max, p.offsets) == (6, 4096, 5120, 1)
     finally:
