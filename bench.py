@@ -340,6 +340,9 @@ def main() -> int:
     K, W = args.steps, args.warmup
     bufs = [(pristine.clone(), None if pay0 is None else pay0.clone()) for _ in range(K + W)]
     params, source = choose_params(binar, args, kb, has_pay, n, batched=False)
+    if name.startswith("f32"):
+        # IEEE-754 keys: same kernels, keys read through the order-preserving view
+        params = binar.Params(**{**vars(params), "key_kind": binar.KEY_FLOAT})
     ws = binar.Workspace(binar.workspace_bytes(kb, n, has_pay, 1, params), device=dev)
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
@@ -372,9 +375,12 @@ def main() -> int:
     if st["status"] != 0:
         raise RuntimeError("sort reported status %d" % st["status"])
 
-    # the last sorted batch must be sorted (unsigned order) -- a cheap sanity check
+    # the last sorted batch must be sorted (in its key order) -- a cheap sanity check
     last = bufs[-1][0]
-    if kb == 4:
+    if name.startswith("f32"):
+        v = last.view(torch.float32)
+        ok = bool((v[1:] >= v[:-1]).all().item())
+    elif kb == 4:
         u = last.to(torch.int64) & 0xFFFFFFFF
         ok = bool((u[1:] >= u[:-1]).all().item())
     else:
@@ -435,7 +441,7 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u32" if kb == 4 else ("u64" if kb == 8 else "u8x16"),
+        "dtype": "f32" if name.startswith("f32") else ("u32" if kb == 4 else ("u64" if kb == 8 else "u8x16")),
         "data": "synthetic",
         "config": {"workload": "%s: %s" % (name, desc), "n": n, "key_bytes": kb, "payload_bytes": pb,
                    **describe_params(binar, kb, has_pay, params, source),

@@ -30,14 +30,13 @@ from __future__ import annotations
 
 import threading
 import time
-from collections import deque
+from collections import defaultdict, deque
 from concurrent.futures import Future
 from dataclasses import dataclass
 
-from .binar import BINAR_ENOMEM, BinarError, key_bytes_of
+from .binar import BINAR_ENOMEM, KEY_FLOAT, KEY_UNSIGNED, BinarError, key_bytes_of
 
 META_BYTES = 256
-WIDTHS = (4, 8, 16)
 
 
 def request_cost(key_bytes: int, n: int) -> int:
@@ -71,6 +70,12 @@ class _Req:
     ready_event: object = None
     admitted: float = 0.0
     launched: float = 0.0
+    kind: int = 0
+
+    @property
+    def cls(self):
+        """Requests batch together when their key width and kind agree."""
+        return (self.kb, self.kind)
 
 
 class Admission:
@@ -125,7 +130,7 @@ class Server:
         self.backend = backend if backend is not None else DeviceBackend(
             streams, self.max_batch_keys, self.max_batch_requests, params_lookup, check_status=check_status)
         self._cv = threading.Condition()
-        self._ready = {kb: deque() for kb in WIDTHS}
+        self._ready = defaultdict(deque)   # (key width, key kind) -> admitted requests
         self._inflight: list = []
         self._next_id = 0
         self._running = True
@@ -137,11 +142,17 @@ class Server:
         self._thread.start()
 
     # ------------------------------------------------------------ client side
-    def submit(self, keys) -> Future:
+    def submit(self, keys, key_kind: int | None = None) -> Future:
         """Queue one request.  `keys` is not modified; the caller must not
-        modify it either until the Future is done."""
+        modify it either until the Future is done.  key_kind: KEY_* of
+        binar.py; default KEY_FLOAT for floating-point tensors, else
+        KEY_UNSIGNED."""
         kb = key_bytes_of(keys)
         n = int(keys.shape[0])
+        if key_kind is None:
+            key_kind = KEY_FLOAT if keys.is_floating_point() else KEY_UNSIGNED
+        if kb == 16 and key_kind != KEY_UNSIGNED:
+            raise ValueError("16-byte keys are byte strings: key_kind must be KEY_UNSIGNED")
         if n > self.max_batch_keys:
             raise BinarError(BINAR_ENOMEM)
         fut: Future = Future()
@@ -150,7 +161,7 @@ class Server:
                 raise RuntimeError("server is closed")
             if self._error is not None:
                 raise RuntimeError("server failed") from self._error
-            req = _Req(self._next_id, keys, kb, n, request_cost(kb, n), fut, self.clock())
+            req = _Req(self._next_id, keys, kb, n, request_cost(kb, n), fut, self.clock(), kind=key_kind)
             req.ready_event = self.backend.mark_ready(keys)
             self.admission.offer(req)      # raises BINAR_ENOMEM for a request that can never fit
             self._next_id += 1
@@ -199,7 +210,7 @@ class Server:
                 with self._cv:
                     now = self.clock()
                     for r in self.admission.admit(now):
-                        self._ready[r.kb].append(r)
+                        self._ready[r.cls].append(r)
                         progressed = True
                     self._drop_cancelled()
                     batches = self._form_batches()
@@ -245,7 +256,7 @@ class Server:
                     r.future.set_exception(e)
 
     def _drop_cancelled(self):
-        for kb, q in self._ready.items():
+        for cls, q in self._ready.items():
             if any(r.future.cancelled() for r in q):
                 keep = deque()
                 for r in q:
@@ -253,13 +264,13 @@ class Server:
                         self.admission.release(r.cost)
                     else:
                         keep.append(r)
-                self._ready[kb] = keep
+                self._ready[cls] = keep
 
     def _form_batches(self) -> list:
         out = []
-        for kb, q in self._ready.items():
+        for cls, q in self._ready.items():
             while q:
-                lane = self.backend.free_lane(kb)
+                lane = self.backend.free_lane(cls)
                 if lane is None:
                     break
                 reqs, keys = [], 0
@@ -294,10 +305,11 @@ class _Lane:
     segment table (device and pinned host copy), a plan whose graph is
     captured on the first batch and replayed for every later one."""
 
-    def __init__(self, kb: int, cap: int, max_segments: int, device, params):
+    def __init__(self, kb: int, kind: int, cap: int, max_segments: int, device, params):
         import torch
-        from .binar import Plan
-        self.kb, self.cap, self.max_segments = kb, cap, max_segments
+        from .binar import Params, Plan
+        self.kb, self.kind, self.cap, self.max_segments = kb, kind, cap, max_segments
+        params = Params(**{**(vars(params) if params is not None else {}), "key_kind": kind})
         self.stream = torch.cuda.Stream(device=device)
         if kb == 16:
             self.keys = torch.empty((cap, 16), dtype=torch.uint8, device=device)
@@ -324,7 +336,7 @@ class DeviceBackend:
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         self.streams, self.cap, self.max_segments = streams, cap, max_segments
         self.params_lookup = params_lookup
-        self.lanes = {kb: [] for kb in WIDTHS}
+        self.lanes = defaultdict(list)     # (key width, key kind) -> lanes
 
     def thread_init(self):
         self.torch.cuda.set_device(self.device)
@@ -343,15 +355,16 @@ class DeviceBackend:
         ev.record()
         return ev
 
-    def free_lane(self, kb):
-        for lane in self.lanes[kb]:
+    def free_lane(self, cls):
+        kb, kind = cls
+        for lane in self.lanes[cls]:
             if not lane.busy:
                 lane.busy = True
                 return lane
-        if len(self.lanes[kb]) < self.streams:
+        if len(self.lanes[cls]) < self.streams:
             params = None if self.params_lookup is None else self.params_lookup(kb, self.cap)
-            lane = _Lane(kb, self.cap, self.max_segments, self.device, params)
-            self.lanes[kb].append(lane)
+            lane = _Lane(kb, kind, self.cap, self.max_segments, self.device, params)
+            self.lanes[cls].append(lane)
             lane.busy = True
             return lane
         return None
@@ -370,7 +383,8 @@ class DeviceBackend:
                 if r.ready_event is not None:
                     lane.stream.wait_event(r.ready_event)
                 if r.n:
-                    lane.keys[pos:pos + r.n].copy_(r.keys, non_blocking=True)
+                    # bits, not values: a float request lands in the integer lane unchanged
+                    lane.keys[pos:pos + r.n].copy_(r.keys.view(lane.keys.dtype), non_blocking=True)
                     if r.keys.is_cuda:
                         r.keys.record_stream(lane.stream)
                 pos += r.n
@@ -388,7 +402,7 @@ class DeviceBackend:
             out_perm = lane.pay[:pos] - torch.repeat_interleave(starts, lens, output_size=pos)
             start = 0
             for r in reqs:
-                outs.append((out_keys[start:start + r.n], out_perm[start:start + r.n]))
+                outs.append((out_keys[start:start + r.n].view(r.keys.dtype), out_perm[start:start + r.n]))
                 start += r.n
             lane.done.record(lane.stream)
         return (lane, outs)

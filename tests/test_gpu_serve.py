@@ -97,3 +97,39 @@ def test_one_request_per_launch_matches():
         res = [f.result(timeout=120) for f in [srv.submit(t) for t in dev]]
     assert all(r.batch_requests == 1 for r in res)
     check_against_alone(host, dev, res, oracle_every=5)
+
+
+def test_key_kinds_in_the_mix():
+    """Float and signed requests share the server with unsigned ones; each
+    result equals the same request sorted alone and the oracle's order."""
+    import torch
+    import paper_0811_3448_amd as binar
+    from oracle import orders
+    from paper_0811_3448_amd.serve import Server
+    rng = np.random.default_rng(9)
+    reqs = []
+    for i in range(30):
+        n = int(rng.integers(1, 20_000))
+        kind = i % 3
+        if kind == 0:
+            t = torch.from_numpy(rng.standard_normal(n).astype(np.float32)).cuda()
+            reqs.append((t, None, orders.FLOAT))
+        elif kind == 1:
+            t = torch.from_numpy(rng.integers(-1000, 1000, n).astype(np.int64)).cuda()
+            reqs.append((t, binar.KEY_SIGNED, orders.SIGNED))
+        else:
+            t = torch.from_numpy((rng.standard_normal(n) * 1e300).astype(np.float64)).cuda()
+            reqs.append((t, None, orders.FLOAT))
+    with Server(budget_bytes=1 << 28, streams=2, max_batch_keys=1 << 18, check_status=True) as srv:
+        res = [f.result(timeout=120) for f in [srv.submit(t, key_kind=k) for t, k, _ in reqs]]
+    for (t, k, ok), r in zip(reqs, res):
+        a = t.clone()
+        p = torch.arange(t.shape[0], dtype=torch.int32, device="cuda")
+        binar.sort(a, p, key_kind=k)
+        torch.cuda.synchronize()
+        assert r.keys.dtype == t.dtype
+        assert torch.equal(r.keys.view(torch.uint8), a.view(torch.uint8))
+        assert torch.equal(r.perm, p)
+        bits = t.cpu().numpy().view(np.uint32 if t.element_size() == 4 else np.uint64)
+        rk, rp = orders.sort(bits, np.arange(t.shape[0], dtype=np.uint32), ok)
+        assert np.array_equal(r.perm.cpu().numpy().view(np.uint32), rp)

@@ -28,7 +28,7 @@ class HostBackend:
 
     def __init__(self, lanes=1, gate=None):
         self.lanes, self.gate = lanes, gate
-        self.busy = {kb: 0 for kb in (4, 8, 16)}
+        self.busy = {}
         self.batches = []
         self.lane_block = threading.Event()
         self.lane_block.set()
@@ -39,17 +39,17 @@ class HostBackend:
     def mark_ready(self, keys):
         return None
 
-    def free_lane(self, kb):
-        if not self.lane_block.is_set() or self.busy[kb] >= self.lanes:
+    def free_lane(self, cls):
+        if not self.lane_block.is_set() or self.busy.get(cls, 0) >= self.lanes:
             return None
-        self.busy[kb] += 1
-        return kb
+        self.busy[cls] = self.busy.get(cls, 0) + 1
+        return cls
 
-    def release_lane(self, kb):
-        self.busy[kb] -= 1
+    def release_lane(self, cls):
+        self.busy[cls] -= 1
 
-    def launch(self, kb, reqs):
-        self.batches.append((kb, [r.id for r in reqs]))
+    def launch(self, cls, reqs):
+        self.batches.append((cls[0], [r.id for r in reqs]))
         return [np_stable(r.keys) for r in reqs]
 
     def poll(self, h):
@@ -197,7 +197,7 @@ def test_no_batching_is_one_request_per_launch():
 
 def test_backend_failure_fails_pending_requests():
     class Broken(HostBackend):
-        def launch(self, kb, reqs):
+        def launch(self, cls, reqs):
             raise RuntimeError("device lost")
     srv = Server(1 << 30, backend=Broken())
     f = srv.submit(u32(10, 1))
@@ -216,3 +216,21 @@ def test_report_percentiles():
     assert rep["requests"] == 50 and rep["keys"] == 5000
     assert 0 <= rep["p50_s"] <= rep["p99_s"] <= rep["max_s"]
     assert rep["throughput_keys_s"] > 0
+
+
+def test_key_kinds_batch_apart():
+    """Float and integer requests of one width never share a batch."""
+    be = HostBackend(lanes=1)
+    be.lane_block.clear()
+    with Server(1 << 30, backend=be) as srv:
+        fi = [srv.submit(u32(10, i)) for i in range(3)]
+        ff = [srv.submit(torch.randn(10)) for _ in range(3)]
+        fs = [srv.submit(u32(10, 9), key_kind=1)]
+        time.sleep(0.05)
+        be.lane_block.set()
+        for f in fi + ff + fs:
+            f.result(timeout=10)
+    groups = [sorted(ids) for _, ids in be.batches]
+    assert sorted(groups) == [[0, 1, 2], [3, 4, 5], [6]]
+    with pytest.raises(ValueError):
+        Server(1 << 30, backend=HostBackend()).submit(torch.zeros((4, 16), dtype=torch.uint8), key_kind=2)

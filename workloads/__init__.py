@@ -152,6 +152,15 @@ def small_alphabet_u32(n: int, seed: int, alphabet) -> np.ndarray:
     return alphabet[below(n, seed, len(alphabet)).astype(np.int64)]
 
 
+def f32_normal(n: int, seed: int) -> np.ndarray:
+    """float32 draws from N(0, 1) (Box-Muller on two uniform streams), as
+    uint32 bit patterns."""
+    u1 = (stream_u64(seed, n) >> np.uint64(11)).astype(np.float64) * (1.0 / (1 << 53))
+    u2 = (stream_u64(seed + 1, n) >> np.uint64(11)).astype(np.float64) * (1.0 / (1 << 53))
+    z = np.sqrt(-2.0 * np.log1p(-u1)) * np.cos(2.0 * np.pi * u2)
+    return z.astype(np.float32).view(np.uint32)
+
+
 # ------------------------------------------------------------ named workloads
 # Each entry: name -> (key_bytes, n, has_payload, description).  Seeds are
 # BASE_SEED + the workload's index in this table.
@@ -163,6 +172,7 @@ SINGLE = {
     "u64_2e27_uniform": (8, 1 << 27, True, "2^27 uniform u64 + u32 index payload"),
     "u64_2e27_nearly_sorted": (8, 1 << 27, True, "2^27 sorted u64 with 1% positions swapped + index"),
     "u64_2e27_zipf": (8, 1 << 27, True, "2^27 u64 Zipf(1.1) over 2^20 distinct values + index"),
+    "f32_2e28_normal": (4, 1 << 28, True, "2^28 float32 N(0, 1) values (IEEE-754 order) + index payload"),
 }
 
 
@@ -172,6 +182,8 @@ def single_keys(name: str, n: int | None = None) -> np.ndarray:
     n = n_full if n is None else n
     seed = BASE_SEED + list(SINGLE).index(name)
     dist = name.split("_", 2)[2]
+    if name.startswith("f32"):
+        return f32_normal(n, seed)
     if kb == 4:
         if dist.startswith("uniform"):
             return u32_uniform(n, seed)
