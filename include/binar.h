@@ -22,8 +22,8 @@
  *   key_bytes == 4  : uint32 values (native little-endian), numeric order;
  *   key_bytes == 8  : uint64 values (native little-endian), numeric order;
  *   key_bytes == 16 : 16-byte strings, memcmp order.
- * Signed and floating-point keys are not reinterpreted: their bit patterns
- * sort as unsigned integers.
+ * 4- and 8-byte keys may instead be read as two's-complement integers or as
+ * IEEE-754 values (binar_params.key_kind).
  *
  * Memory and ownership:
  *   keys, payload, seg_offsets are DEVICE pointers owned by the caller; keys
