@@ -128,6 +128,9 @@ typedef struct binar_stats {
     uint64_t finish_class_keys[4];     /* finish_keys split by LDS size class */
     uint64_t finish_class_segments[4];
     uint64_t copyback_keys;            /* finished keys copied from scratch to the caller's buffer */
+    uint64_t sorted_keys;              /* keys of sub-arrays found already in order by a digit count
+                                          and retired without partitioning (section "Optimize the
+                                          Algorithm") */
 } binar_stats;
 
 /* One timed kernel launch (see binar_profile_enable). */

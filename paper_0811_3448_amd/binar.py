@@ -28,7 +28,7 @@ class _Stats(ctypes.Structure):
                 ("finish_keys", ctypes.c_uint64), ("finish_segments", ctypes.c_uint64),
                 ("passes", ctypes.c_uint32), ("status", ctypes.c_int32),
                 ("finish_class_keys", ctypes.c_uint64 * 4), ("finish_class_segments", ctypes.c_uint64 * 4),
-                ("copyback_keys", ctypes.c_uint64)]
+                ("copyback_keys", ctypes.c_uint64), ("sorted_keys", ctypes.c_uint64)]
 
 
 class _LaunchTime(ctypes.Structure):
@@ -247,7 +247,8 @@ def _stats_dict(s: "_Stats") -> dict:
     return {"moved": list(s.moved), "hist_keys": list(s.hist_keys), "finish_keys": s.finish_keys,
             "finish_segments": s.finish_segments, "passes": s.passes, "status": s.status,
             "finish_class_keys": list(s.finish_class_keys),
-            "finish_class_segments": list(s.finish_class_segments), "copyback_keys": s.copyback_keys}
+            "finish_class_segments": list(s.finish_class_segments), "copyback_keys": s.copyback_keys,
+            "sorted_keys": s.sorted_keys}
 
 
 class Plan:

@@ -99,7 +99,7 @@ struct Resolved {
 };
 
 struct Layout {
-    size_t ctl, list[2], counts[2], bases[2], andor[2], pcnt, status, fin[NCLASS], cpy, keys_b, pay_b, total;
+    size_t ctl, list[2], counts[2], bases[2], andor[2], desc[2], pcnt, status, fin[NCLASS], cpy, keys_b, pay_b, total;
     uint32_t max_big, max_tiles, max_fin[NCLASS], fin_cap[NCLASS], max_cpy;
 };
 
@@ -173,6 +173,7 @@ Layout make_layout(const Resolved &r, uint64_t n) {
         L.counts[i] = take((size_t)L.max_big * R * 4);
         L.bases[i] = take((size_t)L.max_big * R * 4);
         L.andor[i] = take((size_t)L.max_big * 32);
+        L.desc[i] = take((size_t)L.max_big * 4);
     }
     L.pcnt = take((size_t)L.max_tiles * R * 4);
     L.status = take(r.lookback ? (size_t)L.max_tiles * R * 4 : 0);
@@ -270,6 +271,7 @@ Work make_work(const Layout &L, const Resolved &r, char *ws, void *keys, uint32_
         w.counts[i] = reinterpret_cast<uint32_t *>(ws + L.counts[i]);
         w.bases[i] = reinterpret_cast<uint32_t *>(ws + L.bases[i]);
         w.andor[i] = reinterpret_cast<unsigned long long *>(ws + L.andor[i]);
+        w.desc[i] = reinterpret_cast<uint32_t *>(ws + L.desc[i]);
     }
     w.pcnt = reinterpret_cast<uint32_t *>(ws + L.pcnt);
     w.status = reinterpret_cast<uint32_t *>(ws + L.status);
@@ -700,6 +702,7 @@ int binar_stats_read(const void *workspace, void *stream, binar_stats *out) {
     }
     out->passes = c.passes;
     out->copyback_keys = c.cpy_keys;
+    out->sorted_keys = c.sorted_keys;
     out->status = (c.error & ERR_SEGMENTS) ? BINAR_EINVAL
                   : ((c.error & ERR_INTERNAL) || c.overflow) ? BINAR_EDEVICE : BINAR_OK;
     return BINAR_OK;

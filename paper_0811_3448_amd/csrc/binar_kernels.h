@@ -88,6 +88,7 @@ struct Ctl {
     unsigned int cpy_ctr;            // copy-back ranges
     unsigned int pad;
     unsigned long long cpy_keys;
+    unsigned long long sorted_keys;  // keys of segments found already in order
 };
 
 // A range [begin, begin + len) to copy from B to A after the passes.
@@ -101,6 +102,7 @@ struct Work {
     uint32_t *counts[2];           // [entry][radix]: digit totals of the segment
     uint32_t *bases[2];            // [entry][radix]: bucket start (global index)
     unsigned long long *andor[2];  // [entry][4]: and.hi, and.lo, or.hi, or.lo
+    uint32_t *desc[2];             // [entry]: nonzero once two adjacent keys are found out of order
     uint32_t *pcnt;                // [tile][radix]: piece counts -> piece prefixes (row = piece's first tile)
     uint32_t *status;              // [tile][radix]: look-back words (look-back variant only)
     FinEntry *fin[NCLASS];
@@ -278,6 +280,7 @@ __device__ void block_append(const Work &w, int Lnext, int cat, uint32_t begin, 
         if (slot < w.max_big && ts + ntiles <= w.max_tiles) {
             w.list[Lnext][slot] = SegEntry{begin, len, bitpos | (parity << 8), ts};
             unsigned long long *ao = w.andor[Lnext] + (size_t)slot * 4;
+            w.desc[Lnext][slot] = 0u;
             ao[0] = ~0ull;
             ao[1] = ~0ull;
             ao[2] = 0ull;
@@ -366,6 +369,34 @@ __device__ __forceinline__ void load_vec(const void *p, size_t i, typename KeyT<
     }
 }
 
+// The key held by the lane below (lane 0: unspecified).  4- and 8-byte keys
+// move with a DPP wave shift (a VALU op); 16-byte keys through the LDS
+// crossbar.
+template <int KB>
+__device__ __forceinline__ typename KeyT<KB>::V shfl_up_key(typename KeyT<KB>::V v) {
+    constexpr int WAVE_SHR1 = 0x138;
+    if constexpr (KB == 4) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, WAVE_SHR1, 0xF, 0xF, false);
+    } else if constexpr (KB == 8) {
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, WAVE_SHR1, 0xF, 0xF, false);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), WAVE_SHR1, 0xF, 0xF,
+                                                                  false);
+        return ((uint64_t)hi << 32) | lo;
+    } else {
+        return U128{(uint64_t)__shfl_up((long long)v.hi, 1u, WAVE), (uint64_t)__shfl_up((long long)v.lo, 1u, WAVE)};
+    }
+}
+
+// a comes after b in the sort order of the leading bits selected by m (all
+// bits when `full`: then a plain integer compare for 4- and 8-byte keys).
+template <int KB>
+__device__ __forceinline__ bool key_after(typename KeyT<KB>::V a, typename KeyT<KB>::V b, Canon m, bool full) {
+    if constexpr (KB != 16) {
+        if (full) return a > b;
+    }
+    return canon_after(KeyT<KB>::canon(a), KeyT<KB>::canon(b), m);
+}
+
 // Key i of a buffer in the sorting view (enc), and back.
 template <int KB>
 __device__ __forceinline__ typename KeyT<KB>::V ld_key(const void *p, size_t i, uint32_t kind) {
@@ -425,6 +456,11 @@ __global__ __launch_bounds__(BT) void k_hist(Work w, int L) {
         const int wbits = min(K, (int)w.nbits - (int)bitpos);
         const uint32_t kind = w.kind;
         const void *src = w.keys[parity];
+        // already in order?  every key after the segment's first against its
+        // predecessor, in the leading bits being sorted
+        const Canon km = canon_lead_mask((int)w.nbits);
+        const bool full = w.nbits == 8u * KB;
+        bool desc = false;
         const size_t g0 = (size_t)seg.begin + (size_t)(t - seg.tile_start) * w.tile_keys;
         const size_t g1 = (size_t)seg.begin + min((size_t)seg.len, (size_t)(te - seg.tile_start) * w.tile_keys);
         V a = KT::ones(), o = KT::zero();
@@ -435,30 +471,46 @@ __global__ __launch_bounds__(BT) void k_hist(Work w, int L) {
         const size_t b1 = b0 + (g1 - b0) / VN * VN;
         for (size_t i = g0 + threadIdx.x; i < b0; i += BT) {
             const V v = ld_key<KB>(src, i, kind);
+            if (i > seg.begin) desc |= key_after<KB>(ld_key<KB>(src, i - 1, kind), v, km, full);
             atomicAdd(&s_h[wv][KT::digit(v, bitpos, wbits)], 1u);
             a = KT::vand(a, v);
             o = KT::vor(o, v);
         }
         for (size_t i = b1 + threadIdx.x; i < g1; i += BT) {
             const V v = ld_key<KB>(src, i, kind);
+            if (i > seg.begin) desc |= key_after<KB>(ld_key<KB>(src, i - 1, kind), v, km, full);
             atomicAdd(&s_h[wv][KT::digit(v, bitpos, wbits)], 1u);
             a = KT::vand(a, v);
             o = KT::vor(o, v);
         }
         for (size_t i = b0 + (size_t)threadIdx.x * VN; i < b1; i += (size_t)BT * VN * U) {
             V v[U][VN];
+            V pv[U];  // the key before the vector, where no lane below holds it
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const size_t x = i + (size_t)u * BT * VN;
                 if (x < b1) load_vec<KB>(src, x, v[u]);
+                if (x < b1 && (lane == 0 || x == b0) && x > seg.begin) pv[u] = KT::load(src, x - 1);
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const size_t x = i + (size_t)u * BT * VN;
+                // the key before this vector: the last of the lane below's vector
+                // (same step), loaded directly for lane 0 and for the body's first
+                // vector
+                const V pl = shfl_up_key<KB>(v[u][VN - 1]);
                 if (x < b1) {
+                    if (kind) {
+#pragma unroll
+                        for (int q = 0; q < VN; ++q) v[u][q] = KT::enc(v[u][q], kind);
+                    }
+                    V prev = (lane == 0 || x == b0) ? pv[u] : pl;
+                    if (kind) prev = KT::enc(prev, kind);
+                    if (x > seg.begin) desc |= key_after<KB>(prev, v[u][0], km, full);
+#pragma unroll
+                    for (int q = 1; q < VN; ++q) desc |= key_after<KB>(v[u][q - 1], v[u][q], km, full);
 #pragma unroll
                     for (int q = 0; q < VN; ++q) {
-                        if (kind) v[u][q] = KT::enc(v[u][q], kind);
                         atomicAdd(&s_h[wv][KT::digit(v[u][q], bitpos, wbits)], 1u);
                         a = KT::vand(a, v[u][q]);
                         o = KT::vor(o, v[u][q]);
@@ -481,7 +533,7 @@ __global__ __launch_bounds__(BT) void k_hist(Work w, int L) {
             s_ao[wv][2] = co.hi;
             s_ao[wv][3] = co.lo;
         }
-        __syncthreads();
+        if (__syncthreads_or(desc ? 1 : 0) && threadIdx.x == 0) atomicOr(&w.desc[L][slot], 1u);
         uint32_t *row = w.pcnt + (size_t)t * R;
         for (int d = threadIdx.x; d < R; d += BT) {
             uint32_t c = 0;
@@ -594,7 +646,7 @@ __global__ __launch_bounds__(THREADS) void k_plan(Work w, int L, int pass) {
     const int d = threadIdx.x;
     // statistics: summed per block, one atomic each at the end (per-segment
     // atomics on one address serialise the whole grid)
-    unsigned long long st_hist = 0ull, st_moved = 0ull;
+    unsigned long long st_hist = 0ull, st_moved = 0ull, st_sorted = 0ull;
 
     for (uint32_t s = blockIdx.x; s < nslots; s += gridDim.x) {
         const SegEntry seg = w.list[L][s];
@@ -606,6 +658,24 @@ __global__ __launch_bounds__(THREADS) void k_plan(Work w, int L, int pass) {
         const unsigned long long *ao = w.andor[L] + (size_t)s * 4;
         const Canon diff{ao[0] ^ ao[2], ao[1] ^ ao[3]};
         st_hist += seg.len;
+
+        if (w.desc[L][s] == 0u) {
+            // already in order (section "Optimize the Algorithm": a sorted
+            // sub-array needs no partitioning): in A it is done; in B a stable
+            // partition of sorted keys is the identity, so the scatter copies
+            // it to A and no child goes on
+            uint32_t total;
+            const uint32_t excl = block_excl_scan(c, s_tmp, &total);
+            if (parity == 1u) {
+                if (c != 0u) w.bases[L][(size_t)s * R + d] = seg.begin + excl;
+                st_moved += seg.len;
+            } else if (d == 0) {
+                w.list[L][s].info = seg.info | (SEG_SKIP << 16);
+            }
+            st_sorted += seg.len;
+            block_append<R>(w, L ^ 1, -1, 0u, 0u, 0u, 0u, s_tmp, s_base);
+            continue;
+        }
 
         if (nz == 1) {
             // pass-through: every key has the same digit here
@@ -675,6 +745,7 @@ __global__ __launch_bounds__(THREADS) void k_plan(Work w, int L, int pass) {
     if (d == 0) {
         if (st_hist) atomicAdd(&ctl->hist_keys[ps], st_hist);
         if (st_moved) atomicAdd(&ctl->moved[ps], st_moved);
+        if (st_sorted) atomicAdd(&ctl->sorted_keys, st_sorted);
     }
 }
 
@@ -1258,15 +1329,6 @@ __device__ __forceinline__ void lds_passes(FinishLds<KB, BT, ITEMS, PAY> &S, Can
         for (int i = lane; i < R; i += WAVE) S.wh[wv][i] = 0u;
         hib = last_set_below(diff, bitpos, lo);
     }
-}
-
-// a and b agree on the bits set in m
-__device__ __forceinline__ bool canon_eq_under(Canon a, Canon b, Canon m) {
-    return (((a.hi ^ b.hi) & m.hi) | ((a.lo ^ b.lo) & m.lo)) == 0ull;
-}
-
-__device__ __forceinline__ bool canon_less(Canon a, Canon b) {
-    return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo);
 }
 
 // The segment in S is sorted stably by its bits [0, pe]: keys equal on them

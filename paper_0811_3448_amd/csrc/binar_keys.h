@@ -166,6 +166,28 @@ __device__ __forceinline__ int first_set_from(Canon d, int pos, int limit) {
     return limit;
 }
 
+// a and b agree on the bits set in m
+__device__ __forceinline__ bool canon_eq_under(Canon a, Canon b, Canon m) {
+    return (((a.hi ^ b.hi) & m.hi) | ((a.lo ^ b.lo) & m.lo)) == 0ull;
+}
+
+__device__ __forceinline__ bool canon_less(Canon a, Canon b) {
+    return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo);
+}
+
+// The leading `bits` bits (MSB-first) of a left-aligned word.
+__device__ __forceinline__ Canon canon_lead_mask(int bits) {
+    Canon m;
+    m.hi = bits >= 64 ? ~0ull : (bits <= 0 ? 0ull : ~(~0ull >> bits));
+    m.lo = bits >= 128 ? ~0ull : (bits <= 64 ? 0ull : ~(~0ull >> (bits - 64)));
+    return m;
+}
+
+// a comes after b in the order of the leading bits selected by m
+__device__ __forceinline__ bool canon_after(Canon a, Canon b, Canon m) {
+    return canon_less(Canon{b.hi & m.hi, b.lo & m.lo}, Canon{a.hi & m.hi, a.lo & m.lo});
+}
+
 // Last bit index in [pos, end) set in d, or -1 if none.
 __device__ __forceinline__ int last_set_below(Canon d, int pos, int end) {
     // mask bits [pos, end) of the 128-bit left-aligned word
