@@ -286,6 +286,120 @@ def bench_serve(args) -> int:
     return 0
 
 
+def linear_fit(xs, ys):
+    """Least-squares line y = a + b x: (a, b, R^2, largest relative residual)."""
+    import numpy as np
+    x, y = np.asarray(xs, dtype=np.float64), np.asarray(ys, dtype=np.float64)
+    b, a = np.polyfit(x, y, 1)
+    pred = a + b * x
+    ss_res = float(((y - pred) ** 2).sum())
+    ss_tot = float(((y - y.mean()) ** 2).sum())
+    return float(a), float(b), 1.0 - ss_res / ss_tot if ss_tot > 0 else 1.0, float(np.max(np.abs(y - pred) / y))
+
+
+def bench_linearity(args) -> int:
+    """The paper's performance experiment (section "Performance of
+    Algorithm"): 32-bit integers from a Mersenne Twister, sizes from 1 to 10
+    million by a fixed step, each timed as the mean of 10 sorts, to show that
+    time grows linearly with N.  Keys only.  The GPU runs every size; the CPU
+    oracle every millionth (one sort each)."""
+    import numpy as np
+    import torch
+    import paper_0811_3448_amd as binar
+
+    lo, hi, step, iters = 1_000_000, 10_000_000, args.lin_step, 10
+    mt = np.random.RandomState(0x0811)          # MT19937
+    full = mt.randint(0, 1 << 32, size=hi, dtype=np.uint64).astype(np.uint32)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    pristine = torch.from_numpy(full.view(np.int32)).to(dev)
+    work = torch.empty_like(pristine)
+    from paper_0811_3448_amd import tune as _tune
+    ws = binar.Workspace(max([binar.workspace_bytes(4, hi, False, 1, c) for c in _tune.candidates(4, False)]
+                             + [binar.workspace_bytes(4, hi, False)]), device=dev)
+    stream = torch.cuda.current_stream()
+    sizes = list(range(lo, hi + 1, step))
+    gpu_ms, passes = [], []
+    cache = None
+    if not args.untuned:
+        from paper_0811_3448_amd import tune
+        cache = tune.TuneCache(arch=tune.device_arch())
+
+    def params_for(n):
+        p = None if cache is None else cache.lookup(4, False, n, False, max_distance=0)
+        return p if p is not None else binar.Params()
+    for _ in range(3):                          # first launches load the code objects
+        work[:lo].copy_(pristine[:lo])
+        binar.sort(work[:lo], workspace=ws)
+    torch.cuda.synchronize()
+    for k, n in enumerate(sizes):
+        tot = 0.0
+        prm = params_for(n)
+        for _ in range(iters):
+            work[:n].copy_(pristine[:n])
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            binar.sort(work[:n], workspace=ws, params=prm)
+            e1.record(stream)
+            e1.synchronize()
+            tot += e0.elapsed_time(e1)
+        gpu_ms.append(tot / iters)
+        passes.append(binar.stats(ws)["passes"])
+        if k % max(1, len(sizes) // 10) == 0:
+            print("bench: linearity n=%d %.4f ms" % (n, gpu_ms[-1]), file=sys.stderr, flush=True)
+    u = work[:hi].to(torch.int64) & 0xFFFFFFFF
+    if not bool((u[1:] >= u[:-1]).all().item()):
+        raise RuntimeError("output not sorted")
+    if args.lin_dump:
+        with open(args.lin_dump, "w") as f:
+            f.write("n,ms,passes\n")
+            for n, m, q in zip(sizes, gpu_ms, passes):
+                f.write("%d,%.5f,%d\n" % (n, m, q))
+    cpu_sizes, cpu_ms = [], []
+    if not args.no_cpu_baseline:
+        import oracle
+        for n in range(lo, hi + 1, 1_000_000):
+            t0 = time.perf_counter()
+            oracle.sort(full[:n].copy())
+            cpu_ms.append((time.perf_counter() - t0) * 1e3)
+            cpu_sizes.append(n)
+            print("bench: linearity oracle n=%d %.1f ms" % (n, cpu_ms[-1]), file=sys.stderr, flush=True)
+    ga, gb, gr2, gdev = linear_fit(sizes, gpu_ms)
+    # the breadth-first passes come in whole numbers: time is a line per
+    # number of global passes, with a step where N / 2^k first exceeds the
+    # LDS-finish threshold
+    by_passes = {}
+    for pc in sorted(set(passes)):
+        xs = [n for n, q in zip(sizes, passes) if q == pc]
+        ys = [m for m, q in zip(gpu_ms, passes) if q == pc]
+        if len(xs) >= 3:
+            a, b, r2, dv = linear_fit(xs, ys)
+            by_passes[str(pc)] = {"sizes": [xs[0], xs[-1]], "intercept_ms": round(a, 4), "ns_per_key": round(b * 1e6, 5),
+                                  "r2": round(r2, 6), "max_rel_residual": round(dv, 4)}
+    result = {
+        "metric": "sort time vs N, MT19937 u32 keys, 1M..10M (linearity)", "value": round(gr2, 6),
+        "unit": "R^2 of a straight-line fit of GPU time to N", "n_gpus": 1, "steps": iters,
+        "warmup": 0, "ms_per_step": round(gpu_ms[-1], 4), "higher_is_better": True, "scaling": "strong",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "linearity: MT19937 u32 keys only, N = %d..%d step %d, mean of %d sorts per N"
+                               % (lo, hi, step, iters), "sizes": len(sizes),
+                   "params_from": "autotune cache per size bucket" if cache is not None else "library defaults"},
+        "gpu": {"intercept_ms": round(ga, 4), "ns_per_key": round(gb * 1e6, 5), "r2": round(gr2, 6),
+                "max_rel_residual": round(gdev, 4),
+                "ms_at_millions": [round(gpu_ms[sizes.index(n)], 4) for n in range(lo, hi + 1, 1_000_000)
+                                   if n in sizes],
+                "gkeys_s_at_10M": round(hi / (gpu_ms[-1] * 1e-3) / 1e9, 3),
+                "by_global_passes": by_passes},
+    }
+    if cpu_ms:
+        ca, cb, cr2, cdev = linear_fit(cpu_sizes, cpu_ms)
+        result["cpu_oracle"] = {"intercept_ms": round(ca, 2), "ns_per_key": round(cb * 1e6, 2), "r2": round(cr2, 6),
+                                "max_rel_residual": round(cdev, 4), "ms_at_millions": [round(x, 1) for x in cpu_ms],
+                                "cores": 1}
+    print(json.dumps(result), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -301,6 +415,8 @@ def main() -> int:
     ap.add_argument("--untuned", action="store_true", help="ignore the autotune cache: library defaults")
     ap.add_argument("--no-per-array", action="store_true", help="batched workload: skip the per-array comparison")
     ap.add_argument("--serve-requests", type=int, default=10000)
+    ap.add_argument("--lin-step", type=int, default=1000, help="linearity workload: size step")
+    ap.add_argument("--lin-dump", default="", help="linearity workload: write n,ms,passes CSV here")
     ap.add_argument("--serve-budget-gib", type=int, default=32)
     args = ap.parse_args()
 
@@ -324,6 +440,8 @@ def main() -> int:
         return bench_batched(args)
     if args.workload == "serve_c5":
         return bench_serve(args)
+    if args.workload == "linearity":
+        return bench_linearity(args)
 
     name = args.workload
     kb, n, has_pay, desc = workloads.SINGLE[name]

@@ -157,6 +157,39 @@ def key_kind_of(keys, params: "Params | None", key_kind: int | None) -> "Params 
     return p
 
 
+_TUNED = {"cache": None, "loaded": False}
+
+
+def tuned_params(key_bytes: int, has_payload: bool, n: int, batched: bool = False) -> "Params | None":
+    """Parameters the autotune cache holds for this case (nearest size bucket
+    within one), for this device; None without a matching cache or when the
+    environment sets BINAR_AUTOTUNE=0."""
+    if os.environ.get("BINAR_AUTOTUNE", "1") == "0":
+        return None
+    if not _TUNED["loaded"]:
+        _TUNED["loaded"] = True
+        try:
+            from . import tune
+            c = tune.TuneCache(arch=tune.device_arch())
+            _TUNED["cache"] = c if c.entries else None
+        except Exception:  # no readable cache for this device: library defaults
+            _TUNED["cache"] = None
+    c = _TUNED["cache"]
+    return None if c is None else c.lookup(key_bytes, has_payload, n, batched, max_distance=1)
+
+
+def _with_tuning(params, key_bytes, has_payload, n, batched):
+    """params as given, or the tuned ones for this case (keeping any key kind)."""
+    if params is not None and (params.digit_bits or params.tile_keys or params.finish_max or params.offsets):
+        return params
+    t = tuned_params(key_bytes, has_payload, n, batched)
+    if t is None:
+        return params
+    if params is not None:
+        t.key_bits, t.key_kind = params.key_bits, params.key_kind
+    return t
+
+
 def _check_tensors(keys, payload):
     if not keys.is_cuda or not keys.is_contiguous():
         raise ValueError("keys must be a contiguous device tensor")
@@ -194,6 +227,9 @@ def sort(keys, payload=None, stream=None, workspace: Workspace | None = None,
     params = key_kind_of(keys, params, key_kind)
     kb = key_bytes_of(keys)
     n = keys.shape[0]
+    if workspace is None:
+        # the library's pool grows to fit: tuned parameters are safe to use
+        params = _with_tuning(params, kb, payload is not None, n, False)
     ws = (None, 0) if workspace is None else (workspace.ptr, workspace.nbytes)
     pp = None if params is None else ctypes.byref(params.c())
     _check(lib.binar_sort_ex(_dev_ptr(keys), kb, n, _dev_ptr(payload), None, 0, pp,
