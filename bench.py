@@ -400,6 +400,66 @@ def bench_linearity(args) -> int:
     return 0
 
 
+def bench_strings(args) -> int:
+    """Variable-length byte strings: 2^24 strings of lowercase letters,
+    lognormal lengths (mean 20 bytes), with no shared prefix and with a
+    shared 40-byte prefix (several 15-byte rounds), sorted into memcmp order
+    with an index payload (the permutation)."""
+    import numpy as np
+    import torch
+    import paper_0811_3448_amd as binar
+    import workloads
+
+    n = 1 << args.str_log2
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    out = {}
+    for label, prefix in (("no_prefix", 0), ("prefix40", 40)):
+        data, offs = workloads.var_strings(n, 0x5771 + prefix, 20.0, 26, prefix)
+        dd = torch.from_numpy(data).to(dev)
+        od = torch.from_numpy(offs.view(np.int32)).to(dev)
+        iota = torch.arange(n, dtype=torch.int32, device=dev)
+        pay = iota.clone()
+        ws = binar.Workspace(binar.strings_workspace_bytes(n), device=dev)
+        for _ in range(args.warmup):
+            pay.copy_(iota)
+            binar.sort_strings(dd, od, pay, workspace=ws)
+        times = []
+        for _ in range(args.steps):
+            pay.copy_(iota)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            binar.sort_strings(dd, od, pay, workspace=ws)
+            e1.record(stream)
+            e1.synchronize()
+            times.append(e0.elapsed_time(e1))
+        ms = float(np.median(times))
+        # sanity: adjacent strings in order (sampled)
+        p = pay.cpu().numpy().view(np.uint32)
+        o = offs.astype(np.int64)
+        for i in np.random.default_rng(1).integers(0, n - 1, 2000):
+            a, b = int(p[i]), int(p[i + 1])
+            sa, sb = data[o[a]:o[a + 1]].tobytes(), data[o[b]:o[b + 1]].tobytes()
+            if sa > sb or (sa == sb and a > b):
+                raise RuntimeError("strings out of order")
+        out[label] = {"ms": round(ms, 3), "gstrings_s": round(n / (ms * 1e-3) / 1e9, 3),
+                      "string_gbytes_s": round(int(offs[-1]) / (ms * 1e-3) / 1e9, 2),
+                      "mean_len": round(int(offs[-1]) / n, 1)}
+        del dd, od, pay, iota, ws
+    result = {
+        "metric": "variable-length string sort throughput (Gstrings/s)", "value": out["no_prefix"]["gstrings_s"],
+        "unit": "Gstrings/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": out["no_prefix"]["ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u8 strings", "data": "synthetic",
+        "config": {"workload": "str_var: 2^%d lowercase strings, lognormal lengths (mean 20 B), u32 index payload"
+                               % args.str_log2, "n": n},
+        "cases": out,
+    }
+    print(json.dumps(result), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -416,6 +476,7 @@ def main() -> int:
     ap.add_argument("--no-per-array", action="store_true", help="batched workload: skip the per-array comparison")
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--lin-step", type=int, default=1000, help="linearity workload: size step")
+    ap.add_argument("--str-log2", type=int, default=24, help="str_var workload: log2 of the string count")
     ap.add_argument("--lin-dump", default="", help="linearity workload: write n,ms,passes CSV here")
     ap.add_argument("--serve-budget-gib", type=int, default=32)
     args = ap.parse_args()
@@ -442,6 +503,8 @@ def main() -> int:
         return bench_serve(args)
     if args.workload == "linearity":
         return bench_linearity(args)
+    if args.workload == "str_var":
+        return bench_strings(args)
 
     name = args.workload
     kb, n, has_pay, desc = workloads.SINGLE[name]

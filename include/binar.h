@@ -220,6 +220,23 @@ int binar_plan_graphs(const binar_plan *plan);
 size_t binar_plan_workspace_bytes(const binar_plan *plan);
 void binar_plan_destroy(binar_plan *plan);
 
+/* Variable-length byte strings (the sort's "strings of average length",
+ * section "Performance Analysis"; memcmp order, a proper prefix before its
+ * extensions, equal strings in input order).  String i is
+ * bytes[offsets[i], offsets[i+1]); bytes and offsets (n + 1 entries,
+ * nondecreasing, at most nbytes) are DEVICE memory and are not modified.
+ * payload (device, n entries) is permuted into the sorted order:
+ * payload_out[i] = payload_in[p(i)]; pass 0..n-1 to receive p.
+ * The strings are partitioned MSD-first 15 bytes at a time, each round
+ * with the fixed-width 16-byte sort on (next 15 bytes, remaining-length
+ * code) keys; only groups still tied go on to the next round.  Blocks
+ * until done (one small device-to-host read per round).  An offsets table
+ * out of order or past nbytes returns BINAR_EINVAL after reading nothing
+ * out of bounds.  workspace may be NULL (pool). */
+int binar_sort_strings(const uint8_t *bytes, uint64_t nbytes, const uint32_t *offsets, uint64_t n,
+                       uint32_t *payload, void *stream, void *workspace, size_t workspace_bytes);
+size_t binar_strings_workspace_bytes(uint64_t n);
+
 /* Static description of a status code. */
 const char *binar_strerror(int status);
 

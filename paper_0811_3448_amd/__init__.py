@@ -25,7 +25,9 @@ from .binar import (  # noqa: F401
     set_default_params,
     sort,
     sort_segmented,
+    sort_strings,
     stats,
     strerror,
+    strings_workspace_bytes,
     workspace_bytes,
 )

@@ -68,6 +68,10 @@ def _load():
     L.binar_plan_destroy.restype = None
     L.binar_strerror.argtypes = [i32]
     L.binar_strerror.restype = ctypes.c_char_p
+    L.binar_sort_strings.argtypes = [vp, u64, vp, u64, vp, vp, vp, sz]
+    L.binar_sort_strings.restype = i32
+    L.binar_strings_workspace_bytes.argtypes = [u64]
+    L.binar_strings_workspace_bytes.restype = sz
     L.binar_last_error.argtypes = []
     L.binar_last_error.restype = ctypes.c_char_p
     for f in ("binar_sort", "binar_sort_async", "binar_sort_segmented", "binar_sort_ex",
@@ -256,6 +260,34 @@ def sort_segmented(keys, seg_offsets, payload=None, stream=None, workspace: Work
     _check(lib.binar_sort_ex(_dev_ptr(keys), kb, n, _dev_ptr(payload), _dev_ptr(seg_offsets), nseg, pp,
                              _stream_ptr(stream), ws[0], ws[1]))
     return keys
+
+
+def strings_workspace_bytes(n: int) -> int:
+    return int(lib.binar_strings_workspace_bytes(n))
+
+
+def sort_strings(data, offsets, payload, stream=None, workspace: Workspace | None = None):
+    """Sort n variable-length byte strings -- string i is
+    data[offsets[i]:offsets[i+1]] -- in memcmp order (a proper prefix
+    first, equal strings in input order) and permute payload with them in
+    place.  data: device uint8 tensor; offsets: device 4-byte tensor of
+    n + 1 offsets; payload: device 4-byte tensor of n entries (pass
+    0..n-1 to receive the sorting permutation).  Blocks until done."""
+    import torch
+    if not data.is_cuda or data.dtype != torch.uint8 or data.dim() != 1 or not data.is_contiguous():
+        raise ValueError("data must be a contiguous 1-D uint8 device tensor")
+    if not offsets.is_cuda or offsets.element_size() != 4 or offsets.dim() != 1 or not offsets.is_contiguous():
+        raise ValueError("offsets must be a contiguous 1-D 4-byte device tensor")
+    n = offsets.shape[0] - 1
+    if n < 0:
+        raise ValueError("offsets needs at least one entry")
+    if not payload.is_cuda or payload.element_size() != 4 or payload.dim() != 1 or payload.shape[0] != n \
+            or not payload.is_contiguous():
+        raise ValueError("payload must be a contiguous 1-D 4-byte device tensor of n entries")
+    ws = (None, 0) if workspace is None else (workspace.ptr, workspace.nbytes)
+    _check(lib.binar_sort_strings(_dev_ptr(data), data.shape[0], _dev_ptr(offsets), n, _dev_ptr(payload),
+                                  _stream_ptr(stream), ws[0], ws[1]))
+    return payload
 
 
 def stats(workspace: Workspace | None = None, stream=None) -> dict:

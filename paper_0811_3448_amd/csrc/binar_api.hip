@@ -18,6 +18,7 @@
 
 #include "binar.h"
 #include "binar_kernels.h"
+#include "binar_strings.h"
 
 namespace binar {
 namespace {
@@ -494,6 +495,104 @@ int run(void *keys, uint32_t kb, uint64_t n, uint32_t *payload, const uint32_t *
     return dispatch(r, w, L, seg_off, seg_off ? nseg : 1u, (uint32_t)n, st);
 }
 
+// ------------------------------------------------------------ strings
+struct StrLayout {
+    size_t ctl, ids, ids_c, pos_c, ids_n, pos_n, seg_c, seg_n, mark, blk, keys, inner, inner_bytes, total;
+};
+
+StrLayout str_layout(uint64_t n) {
+    StrLayout S{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = align_up(off + bytes);
+        return at;
+    };
+    const size_t nblk = (n + STR_BT - 1) / STR_BT + 1;
+    S.ctl = take(sizeof(StrCtl));
+    S.ids = take(4 * n);
+    S.ids_c = take(4 * n);
+    S.pos_c = take(4 * n);
+    S.ids_n = take(4 * n);
+    S.pos_n = take(4 * n);
+    S.seg_c = take(4 * (n + 2));
+    S.seg_n = take(4 * (n + 2));
+    S.mark = take(4 * n);
+    S.blk = take(8 * nblk);
+    S.keys = take(16 * n);
+    Resolved r;
+    (void)resolve(16, true, nullptr, &r);
+    S.inner_bytes = make_layout(r, n < 2 ? 2 : n).total;
+    S.inner = take(S.inner_bytes);
+    S.total = off;
+    return S;
+}
+
+uint32_t grid1d(uint64_t n) { return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((n + 255) / 256, 4096)); }
+
+int sort_strings(const uint8_t *bytes, uint64_t nbytes, const uint32_t *offs, uint64_t n, uint32_t *payload,
+                 hipStream_t st, void *ws, size_t ws_bytes) {
+    if (n > BINAR_MAX_KEYS) return BINAR_ERANGE;
+    if (n < 2) return BINAR_OK;  // base case
+    if (!offs || !payload || (!bytes && nbytes)) return BINAR_EINVAL;
+    const StrLayout L = str_layout(n);
+    int dev = 0;
+    BINAR_HIP_TRY(hipGetDevice(&dev));
+    if (ws) {
+        if (ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & (ALIGN - 1))) return BINAR_ENOMEM;
+    } else if (int rc = pool_get(dev, L.total, &ws)) {
+        return rc;
+    }
+    (void)hipGetLastError();
+    char *b = static_cast<char *>(ws);
+    StrCtl *ctl = reinterpret_cast<StrCtl *>(b + L.ctl);
+    uint32_t *ids = reinterpret_cast<uint32_t *>(b + L.ids);
+    uint32_t *ids_c = reinterpret_cast<uint32_t *>(b + L.ids_c), *ids_n = reinterpret_cast<uint32_t *>(b + L.ids_n);
+    uint32_t *pos_c = reinterpret_cast<uint32_t *>(b + L.pos_c), *pos_n = reinterpret_cast<uint32_t *>(b + L.pos_n);
+    uint32_t *seg_c = reinterpret_cast<uint32_t *>(b + L.seg_c), *seg_n = reinterpret_cast<uint32_t *>(b + L.seg_n);
+    uint32_t *mark = reinterpret_cast<uint32_t *>(b + L.mark);
+    uint32_t *blk = reinterpret_cast<uint32_t *>(b + L.blk);
+    uint8_t *keys = reinterpret_cast<uint8_t *>(b + L.keys);
+    void *inner = b + L.inner;
+    const uint32_t nn = (uint32_t)n;
+    hipLaunchKernelGGL(k_str_iota, dim3(grid1d(n)), dim3(256), 0, st, ids_c, pos_c, mark, seg_c, nn, ctl);
+    uint32_t n_active = nn, nseg = 1, depth = 0, round = 1;
+    for (;;) {
+        hipLaunchKernelGGL(k_str_keys, dim3(grid1d(n_active)), dim3(256), 0, st, bytes, nbytes, offs, nn, ids_c,
+                           n_active, depth, keys, ctl);
+        BINAR_HIP_TRY(hipGetLastError());
+        if (int rc = run(keys, 16, n_active, ids_c, seg_c, nseg, nullptr, st, inner, L.inner_bytes)) return rc;
+        hipLaunchKernelGGL(k_str_place, dim3(grid1d(n_active)), dim3(256), 0, st, ids_c, pos_c, n_active, ids);
+        if (round > 1)
+            hipLaunchKernelGGL(k_str_mark, dim3(grid1d(nseg)), dim3(256), 0, st, seg_c, nseg, mark, round);
+        const uint32_t nblk = (n_active + STR_BT - 1) / STR_BT;
+        hipLaunchKernelGGL(k_str_count, dim3(nblk), dim3(STR_BT), 0, st, reinterpret_cast<const uint4 *>(keys), mark,
+                           round, n_active, blk);
+        hipLaunchKernelGGL(k_str_scan, dim3(1), dim3(STR_BT), 0, st, blk, nblk, ctl);
+        hipLaunchKernelGGL(k_str_compact, dim3(nblk), dim3(STR_BT), 0, st, reinterpret_cast<const uint4 *>(keys),
+                           mark, round, n_active, blk, ids_c, pos_c, ids_n, pos_n, seg_n, ctl);
+        BINAR_HIP_TRY(hipGetLastError());
+        StrCtl h{};
+        BINAR_HIP_TRY(hipMemcpyAsync(&h, ctl, sizeof(h), hipMemcpyDeviceToHost, st));
+        BINAR_HIP_TRY(hipStreamSynchronize(st));
+        if (h.error) return BINAR_EINVAL;
+        if (h.n_next == 0) break;
+        std::swap(ids_c, ids_n);
+        std::swap(pos_c, pos_n);
+        std::swap(seg_c, seg_n);
+        n_active = h.n_next;
+        nseg = h.seg_next;
+        depth += STR_WIN;
+        ++round;
+    }
+    // the payload follows the ids: copy it aside, then gather
+    hipLaunchKernelGGL(k_str_copy, dim3(grid1d(n)), dim3(256), 0, st, payload, nn, ids_n);
+    hipLaunchKernelGGL(k_str_gather, dim3(grid1d(n)), dim3(256), 0, st, ids, ids_n, nn, payload);
+    BINAR_HIP_TRY(hipGetLastError());
+    BINAR_HIP_TRY(hipStreamSynchronize(st));
+    return BINAR_OK;
+}
+
 const void *last_ws(int dev) {
     std::lock_guard<std::mutex> lk(g_pool_mu);
     return (dev < (int)g_last_ws.size()) ? g_last_ws[dev] : nullptr;
@@ -777,6 +876,17 @@ int binar_profile_read(binar_launch_time *out, uint32_t cap, uint32_t *count) {
 }
 
 const char *binar_last_error(void) { return binar::t_err; }
+
+size_t binar_strings_workspace_bytes(uint64_t n) {
+    if (n > BINAR_MAX_KEYS) return 0;
+    return binar::str_layout(n).total;
+}
+
+int binar_sort_strings(const uint8_t *bytes, uint64_t nbytes, const uint32_t *offsets, uint64_t n, uint32_t *payload,
+                       void *stream, void *workspace, size_t workspace_bytes) {
+    return binar::sort_strings(bytes, nbytes, offsets, n, payload, static_cast<hipStream_t>(stream), workspace,
+                               workspace_bytes);
+}
 
 const char *binar_strerror(int status) {
     switch (status) {

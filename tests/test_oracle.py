@@ -387,3 +387,41 @@ def test_kind_planted_mistake_fails():
     wrong = np.where(bits >> 31, -(bits & 0x7FFFFFFF).astype(np.int64), (bits & 0x7FFFFFFF).astype(np.int64))
     wrong = np.where(bits >> 31, -wrong - 1, wrong)   # magnitude order kept for negatives: wrong
     assert not np.array_equal(np.argsort(wrong, kind="stable"), np.argsort(v, kind="stable"))
+
+
+# ---------------------------------------------------- variable-length strings
+
+def test_strings_brute_force():
+    """Every ordering of up to 6 strings over a small alphabet (prefixes,
+    empty strings, equal strings, a zero byte): exactly one is nondecreasing
+    with ties in index order, and the oracle returns it."""
+    from oracle import strings
+    pool = [b"", b"a", b"ab", b"a\x00", b"b", b"ab", b"\x00", b"aa"]
+    rng = np.random.default_rng(3)
+    for trial in range(40):
+        k = int(rng.integers(1, 7))
+        s = [pool[int(i)] for i in rng.integers(0, len(pool), k)]
+        data, offs = strings.pack(s)
+        got = [int(x) for x in strings.stable_order(data, offs)]
+        good = [p for p in itertools.permutations(range(k))
+                if all(s[p[i]] < s[p[i + 1]] or (s[p[i]] == s[p[i + 1]] and p[i] < p[i + 1]) for i in range(k - 1))]
+        assert good == [tuple(got)]
+
+
+def test_strings_prefix_and_zero_bytes():
+    from oracle import strings
+    s = [b"abc", b"ab", b"ab\x00", b"", b"abc\x00\x00", b"b", b"ab"]
+    data, offs = strings.pack(s)
+    p = [int(x) for x in strings.stable_order(data, offs)]
+    assert [s[i] for i in p] == [b"", b"ab", b"ab", b"ab\x00", b"abc", b"abc\x00\x00", b"b"]
+    assert p[1:3] == [1, 6]                      # equal strings keep input order
+
+
+def test_strings_fixed_length_match_lexsort():
+    """Strings of one length: numpy's lexsort over byte columns (stable, last
+    key primary) gives the same order."""
+    from oracle import strings
+    rng = np.random.default_rng(11)
+    a = rng.integers(0, 3, (3000, 7)).astype(np.uint8)
+    data, offs = strings.pack([bytes(r) for r in a])
+    assert np.array_equal(strings.stable_order(data, offs), np.lexsort(a.T[::-1]))

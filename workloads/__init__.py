@@ -218,6 +218,24 @@ def batched_u32(num_segments: int = BATCHED_SEGMENTS, seed: int = BASE_SEED + 3,
     return keys, offsets
 
 
+def var_strings(n: int, seed: int, mean_len: float = 20.0, alphabet: int = 26, shared_prefix: int = 0):
+    """n variable-length strings: lognormal lengths (median mean_len / e^0.18,
+    sigma 0.6, at most 200), lowercase letters from an alphabet of the given
+    size, optionally a prefix of shared_prefix bytes common to all.
+    Returns (data uint8, offsets uint32 of n + 1 entries)."""
+    lens = lognormal_sizes(n, seed, mean_len / np.exp(0.18), 0.6, 0, 200).astype(np.int64)
+    offs = np.zeros(n + 1, dtype=np.uint64)
+    np.cumsum(lens + shared_prefix, out=offs[1:])
+    total = int(offs[-1])
+    letters = (ord("a") + below(total, seed + 1, alphabet)).astype(np.uint8)
+    if shared_prefix:
+        pre = (ord("a") + below(shared_prefix, seed + 2, 26)).astype(np.uint8)
+        starts = offs[:-1].astype(np.int64)
+        for j in range(shared_prefix):
+            letters[starts + j] = pre[j]
+    return letters, offs.astype(np.uint32)
+
+
 SERVE_KINDS = ((4, 0.5), (8, 0.3), (16, 0.2))
 
 
