@@ -188,6 +188,7 @@ def bench_batched(args) -> int:
         "finish_segments": st["finish_segments"], "passes": st["passes"],
         "eager_kernels_ms": kernels,
         "finish_class_segments": st_e["finish_class_segments"], "finish_class_keys": st_e["finish_class_keys"],
+        "finish_small_segments": st_e["finish_small_segments"],
     }
     print(json.dumps(result), flush=True)
     return 0
@@ -576,6 +577,7 @@ def main() -> int:
                   "k_scatter": sum(2 * (kb + pb) * x for x in st["moved"])}
     for c in range(4):
         per_kernel["k_finish%d" % c] = 2 * (kb + pb) * st["finish_class_keys"][c]
+    per_kernel["k_finish_small"] = 2 * (kb + pb) * st["finish_small_keys"]
     total_bytes = sum(per_kernel.values())
 
     agg = {}

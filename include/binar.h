@@ -116,7 +116,8 @@ typedef struct binar_params {
  *   moved[j]       keys scattered by global pass j (pass-through and
  *                  finished sub-arrays move nothing);
  *   hist_keys[j]   keys read by the digit count of pass j;
- *   finish_keys    keys sorted in LDS; finish_segments their sub-arrays;
+ *   finish_keys    keys of sub-arrays finished on chip (LDS classes and the
+ *                  small path); finish_segments their sub-arrays;
  *   passes         global passes that had work. */
 typedef struct binar_stats {
     uint64_t moved[16];
@@ -131,11 +132,14 @@ typedef struct binar_stats {
     uint64_t sorted_keys;              /* keys of sub-arrays found already in order by a digit count
                                           and retired without partitioning (section "Optimize the
                                           Algorithm") */
+    uint64_t finish_small_keys;        /* finish_keys of sub-arrays of 2..64 keys, each ranked inside one
+                                          64-lane wavefront (in no LDS class) */
+    uint64_t finish_small_segments;
 } binar_stats;
 
 /* One timed kernel launch (see binar_profile_enable). */
 typedef struct binar_launch_time {
-    char name[32];   /* "k_hist", "k_plan", "k_scatter", "k_finish0".."k_finish3", ... */
+    char name[32];   /* "k_hist", "k_plan", "k_scatter", "k_finish_small", "k_finish0".."k_finish3", ... */
     int32_t pass;    /* global pass index, -1 for launches outside the pass loop */
     float ms;        /* elapsed time between the events around the launch */
 } binar_launch_time;

@@ -28,7 +28,8 @@ class _Stats(ctypes.Structure):
                 ("finish_keys", ctypes.c_uint64), ("finish_segments", ctypes.c_uint64),
                 ("passes", ctypes.c_uint32), ("status", ctypes.c_int32),
                 ("finish_class_keys", ctypes.c_uint64 * 4), ("finish_class_segments", ctypes.c_uint64 * 4),
-                ("copyback_keys", ctypes.c_uint64), ("sorted_keys", ctypes.c_uint64)]
+                ("copyback_keys", ctypes.c_uint64), ("sorted_keys", ctypes.c_uint64),
+                ("finish_small_keys", ctypes.c_uint64), ("finish_small_segments", ctypes.c_uint64)]
 
 
 class _LaunchTime(ctypes.Structure):
@@ -316,7 +317,8 @@ def _stats_dict(s: "_Stats") -> dict:
             "finish_segments": s.finish_segments, "passes": s.passes, "status": s.status,
             "finish_class_keys": list(s.finish_class_keys),
             "finish_class_segments": list(s.finish_class_segments), "copyback_keys": s.copyback_keys,
-            "sorted_keys": s.sorted_keys}
+            "sorted_keys": s.sorted_keys, "finish_small_keys": s.finish_small_keys,
+            "finish_small_segments": s.finish_small_segments}
 
 
 class Plan:

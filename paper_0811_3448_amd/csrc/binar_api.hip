@@ -100,8 +100,9 @@ struct Resolved {
 };
 
 struct Layout {
-    size_t ctl, list[2], counts[2], bases[2], andor[2], desc[2], pcnt, status, fin[NCLASS], cpy, keys_b, pay_b, total;
-    uint32_t max_big, max_tiles, max_fin[NCLASS], fin_cap[NCLASS], max_cpy;
+    size_t ctl, list[2], counts[2], bases[2], andor[2], desc[2], pcnt, status, fin[NCLASS], fin_small, cpy, keys_b,
+        pay_b, total;
+    uint32_t max_big, max_tiles, max_fin[NCLASS], fin_cap[NCLASS], max_small, max_cpy;
 };
 
 binar_params g_defaults[3][2];  // [kb index][has payload]
@@ -178,7 +179,11 @@ Layout make_layout(const Resolved &r, uint64_t n) {
     }
     L.pcnt = take((size_t)L.max_tiles * R * 4);
     L.status = take(r.lookback ? (size_t)L.max_tiles * R * 4 : 0);
-    uint32_t prev = 1;
+    // sub-arrays of 2 .. SMALL_MAX keys go to the small list, longer ones up
+    // to T to the smallest LDS class that holds them
+    L.max_small = (r.T >= 2u) ? (uint32_t)(n / 2ull + 1ull) : 0u;
+    L.fin_small = take((size_t)L.max_small * sizeof(FinEntry));
+    uint32_t prev = SMALL_MAX;
     for (int c = 0; c < NCLASS; ++c) {
         L.fin_cap[c] = fin_cap(r.kb, c);
         L.max_fin[c] = (prev >= r.T) ? 0u : (uint32_t)(n / (prev + 1ull) + 1ull);
@@ -281,6 +286,8 @@ Work make_work(const Layout &L, const Resolved &r, char *ws, void *keys, uint32_
         w.fin_cap[c] = L.fin_cap[c];
         w.max_fin[c] = L.max_fin[c];
     }
+    w.fin_small = reinterpret_cast<FinEntry *>(ws + L.fin_small);
+    w.max_small = L.max_small;
     w.cpy = reinterpret_cast<CopyEntry *>(ws + L.cpy);
     w.max_cpy = L.max_cpy;
     w.max_big = L.max_big;
@@ -414,6 +421,14 @@ int enqueue(Work w, const Layout &L, const uint32_t *seg_off, uint32_t nseg, uin
     {
         Timed tm(st, "k_copyback", -1);
         hipLaunchKernelGGL((k_copyback<KB, PAY>), dim3(grid_for(k_copyback<KB, PAY>, L.max_cpy)), dim3(THREADS), 0,
+                           st, w);
+    }
+    if (L.max_small) {
+        Timed tm(st, "k_finish_small", -1);
+        // one wave per 64 list entries, at most what fits the device at once
+        const uint32_t waves = (L.max_small + WAVE - 1) / WAVE;
+        hipLaunchKernelGGL((k_finish_small<KB, PAY>),
+                           dim3(grid_for(k_finish_small<KB, PAY>, (waves + WAVES - 1) / WAVES)), dim3(THREADS), 0,
                            st, w);
     }
     launch_finish<KB, PAY, 0>(w, L, st);
@@ -799,6 +814,10 @@ int binar_stats_read(const void *workspace, void *stream, binar_stats *out) {
         out->finish_keys += c.fin_keys[k];
         out->finish_segments += c.fin_segs[k];
     }
+    out->finish_small_keys = c.small_keys;
+    out->finish_small_segments = c.small_segs;
+    out->finish_keys += c.small_keys;
+    out->finish_segments += c.small_segs;
     out->passes = c.passes;
     out->copyback_keys = c.cpy_keys;
     out->sorted_keys = c.sorted_keys;

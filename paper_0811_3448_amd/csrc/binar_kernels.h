@@ -50,6 +50,9 @@ constexpr int WAVE = 64;
 constexpr int THREADS = 256;
 constexpr int WAVES = THREADS / WAVE;
 constexpr int NCLASS = 4;        // LDS-finish size classes
+constexpr uint32_t SMALL_MAX = 64;  // sub-arrays this short are ranked by one wave (k_finish_small)
+constexpr int CAT_SMALL = NCLASS + 1;  // block_append category of such a sub-array
+constexpr int S_BASE_WORDS = NCLASS + 4;  // block_append's shared bases (+ k_plan's copy-back base)
 constexpr int MAX_PASSES = 16;   // statistics slots (128 bits / 8 bits)
 
 constexpr uint32_t SEG_SKIP = 1u;  // segment does not scatter this pass
@@ -89,6 +92,10 @@ struct Ctl {
     unsigned int pad;
     unsigned long long cpy_keys;
     unsigned long long sorted_keys;  // keys of segments found already in order
+    unsigned long long small_keys;   // keys and sub-arrays of k_finish_small
+    unsigned long long small_segs;
+    unsigned int small_ctr;          // entries of the small list
+    unsigned int pad2;
 };
 
 // A range [begin, begin + len) to copy from B to A after the passes.
@@ -106,6 +113,8 @@ struct Work {
     uint32_t *pcnt;                // [tile][radix]: piece counts -> piece prefixes (row = piece's first tile)
     uint32_t *status;              // [tile][radix]: look-back words (look-back variant only)
     FinEntry *fin[NCLASS];
+    FinEntry *fin_small;           // sub-arrays of 2 .. SMALL_MAX keys
+    uint32_t max_small;            // entries the small list can hold
     CopyEntry *cpy;
     uint32_t max_cpy;
     uint32_t fin_cap[NCLASS];      // largest segment of each class
@@ -244,22 +253,24 @@ __global__ void k_reset(Ctl *ctl) {
 
 // Block-aggregated appends of the children a block found: category q of
 // thread's child: 0..NCLASS-1 = LDS-finish class, NCLASS = next pass list,
-// -1 = none.  Each category reserves one contiguous range with one atomic;
-// next-pass entries reserve their list slots and tiles together, so the list
-// stays ordered by tile_start.
+// CAT_SMALL = small list, -1 = none.  Each category reserves one contiguous
+// range with one atomic; next-pass entries reserve their list slots and
+// tiles together, so the list stays ordered by tile_start.  s_base holds
+// S_BASE_WORDS words; word NCLASS + 2 is left to the caller.
 template <int R>
 __device__ void block_append(const Work &w, int Lnext, int cat, uint32_t begin, uint32_t len, uint32_t bitpos,
                              uint32_t parity, uint32_t *s_tmp, uint32_t *s_base) {
-    uint32_t idx[NCLASS + 1];
-    uint32_t tot[NCLASS + 1];
+    uint32_t idx[NCLASS + 2];
+    uint32_t tot[NCLASS + 2];
 #pragma unroll
-    for (int q = 0; q <= NCLASS; ++q) idx[q] = block_excl_scan(cat == q ? 1u : 0u, s_tmp, &tot[q]);
+    for (int q = 0; q <= CAT_SMALL; ++q) idx[q] = block_excl_scan(cat == q ? 1u : 0u, s_tmp, &tot[q]);
     const uint32_t ntiles = (cat == NCLASS) ? (len + w.tile_keys - 1) / w.tile_keys : 0u;
     uint32_t tot_tiles;
     const uint32_t tidx = block_excl_scan(ntiles, s_tmp, &tot_tiles);
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int q = 0; q < NCLASS; ++q) s_base[q] = tot[q] ? atomicAdd(&w.ctl->fin_ctr[q], tot[q]) : 0u;
+        s_base[NCLASS + 3] = tot[CAT_SMALL] ? atomicAdd(&w.ctl->small_ctr, tot[CAT_SMALL]) : 0u;
         if (tot[NCLASS]) {
             const unsigned long long old = atomicAdd(&w.ctl->list_ctr[Lnext],
                                                      ((unsigned long long)tot[NCLASS] << 32) | tot_tiles);
@@ -272,6 +283,12 @@ __device__ void block_append(const Work &w, int Lnext, int cat, uint32_t begin, 
         const uint32_t slot = s_base[cat] + idx[cat];
         if (slot < w.max_fin[cat])
             w.fin[cat][slot] = FinEntry{begin, len | (bitpos << 16) | (parity << 24)};
+        else
+            atomicOr(&w.ctl->overflow, 1u);
+    } else if (cat == CAT_SMALL) {
+        const uint32_t slot = s_base[NCLASS + 3] + idx[CAT_SMALL];
+        if (slot < w.max_small)
+            w.fin_small[slot] = FinEntry{begin, len | (bitpos << 16) | (parity << 24)};
         else
             atomicOr(&w.ctl->overflow, 1u);
     } else if (cat == NCLASS) {
@@ -292,7 +309,10 @@ __device__ void block_append(const Work &w, int Lnext, int cat, uint32_t begin, 
     __syncthreads();
 }
 
+// Where a sub-array of 2 .. T keys is finished: the small list, or the
+// smallest LDS class that holds it.
 __device__ __forceinline__ int fin_class(const Work &w, uint32_t len) {
+    if (len <= SMALL_MAX) return CAT_SMALL;
     int c = 0;
     while (c < NCLASS - 1 && len > w.fin_cap[c]) ++c;
     return c;
@@ -300,12 +320,13 @@ __device__ __forceinline__ int fin_class(const Work &w, uint32_t len) {
 
 // ------------------------------------------------------------------- k_init
 // Classify the caller's segments: <= 1 key: nothing to do (base case);
-// <= T keys: LDS finish; larger: first global pass.
+// <= T keys: finished by one wave (small list) or in LDS; larger: first
+// global pass.
 template <int R>
 __global__ __launch_bounds__(THREADS) void k_init(Work w, const uint32_t *seg_off, uint32_t nseg,
                                                   uint32_t n_single, uint32_t n_limit) {
     __shared__ uint32_t s_tmp[WAVES];
-    __shared__ uint32_t s_base[NCLASS + 2];
+    __shared__ uint32_t s_base[S_BASE_WORDS];
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t s0 = blockIdx.x * blockDim.x; s0 < nseg; s0 += stride) {
         const uint32_t s = s0 + threadIdx.x;
@@ -634,7 +655,7 @@ __global__ __launch_bounds__(THREADS) void k_plan(Work w, int L, int pass) {
     constexpr int R = 1 << K;
     const int NB = (int)w.nbits;
     __shared__ uint32_t s_tmp[WAVES];
-    __shared__ uint32_t s_base[NCLASS + 3];
+    __shared__ uint32_t s_base[S_BASE_WORDS];
     __shared__ uint32_t s_state[THREADS];
     Ctl *ctl = w.ctl;
     if (ctl->error | ctl->overflow) return;
@@ -1503,6 +1524,112 @@ void k_finish(Work w, int cls) {
     if (threadIdx.x == 0 && st_segs) {
         atomicAdd(&ctl->fin_keys[cls], st_keys);
         atomicAdd(&ctl->fin_segs[cls], st_segs);
+    }
+}
+
+// ---------------------------------------------------------- k_finish_small
+// Sub-arrays of 2 .. SMALL_MAX keys.  A block per sub-array would spend its
+// time on barriers; instead each wave takes 64 list entries at a time and
+// packs as many whole sub-arrays as fit into its 64 lanes, one key per lane.
+// A key's place in its sub-array is the number of keys there that come
+// before it in the stable order (smaller on the leading nbits bits, or equal
+// and earlier in the input), so the result is the stable sort.  Every lane
+// loads its key before any lane of the wave stores, and distinct sub-arrays
+// never overlap, so reading and writing the same buffer is safe.
+template <int KB, bool PAY>
+__global__ __launch_bounds__(THREADS) void k_finish_small(Work w) {
+    using KT = KeyT<KB>;
+    using V = typename KT::V;
+    Ctl *ctl = w.ctl;
+    if (ctl->error | ctl->overflow) return;
+    const uint32_t nent = min(ctl->small_ctr, w.max_small);
+    const int lane = lane_id();
+    const uint32_t wave_id = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    const uint32_t nwaves = gridDim.x * (blockDim.x / WAVE);
+    const Canon km = canon_lead_mask((int)w.nbits);
+    unsigned long long st_keys = 0ull, st_segs = 0ull;  // per lane, reduced at the end
+    for (uint32_t e0 = wave_id * WAVE; e0 < nent; e0 += nwaves * WAVE) {
+        // lane l holds entry e0 + l
+        uint32_t b = 0u, len = 0u, par = 0u;
+        if (e0 + lane < nent) {
+            const FinEntry fe = w.fin_small[e0 + lane];
+            b = fe.begin;
+            len = fe.info & 0xFFFFu;
+            par = (fe.info >> 24) & 1u;
+            if (len > SMALL_MAX || (size_t)b + len > w.n_total) {
+                atomicOr(&ctl->error, ERR_INTERNAL);
+                len = 0u;
+            }
+            st_keys += len;
+            ++st_segs;
+        }
+        // inclusive prefix of the lengths: entry l owns keys [incl - len, incl)
+        uint32_t incl = len;
+#pragma unroll
+        for (int o = 1; o < WAVE; o <<= 1) {
+            const uint32_t y = __shfl_up(incl, o, WAVE);
+            if (lane >= o) incl += y;
+        }
+        const uint32_t total = __builtin_amdgcn_readlane(incl, WAVE - 1);
+        for (uint32_t done = 0u; done < total;) {
+            // the entries that end within the next 64 keys (a leading run of
+            // lanes, as incl never decreases); the one holding key `done`
+            // is always among them, since no entry exceeds 64 keys
+            const uint64_t fits = __ballot(incl <= done + WAVE);
+            const int last = 63 - __builtin_clzll(fits);
+            const uint32_t end = __builtin_amdgcn_readlane(incl, last);
+            const uint32_t q = done + (uint32_t)lane;
+            const bool act = q < end;
+            // entry of key q: the number of entries that end at or before q
+            int l = 0;
+#pragma unroll
+            for (int step = WAVE / 2; step > 0; step >>= 1)
+                if ((uint32_t)__shfl(incl, l + step - 1, WAVE) <= q) l += step;
+            const uint32_t eb = __shfl(b, l, WAVE), el = __shfl(len, l, WAVE), ep = __shfl(par, l, WAVE);
+            const uint32_t i = q - ((uint32_t)__shfl(incl, l, WAVE) - el);  // index inside the sub-array
+            const int head = (lane - (int)i) & (WAVE - 1);
+            V k = KT::zero();
+            uint32_t pv = 0u;
+            if (act) {
+                k = ld_key<KB>(w.keys[ep], (size_t)eb + i, w.kind);
+                if constexpr (PAY) pv = w.pay[ep][eb + i];
+            }
+            Canon ck = KT::canon(k);
+            ck.hi &= km.hi;
+            ck.lo &= km.lo;
+            // longest sub-array of this group: the rank loop's trip count
+            uint32_t ml = act ? el : 0u;
+#pragma unroll
+            for (int o = 1; o < WAVE; o <<= 1) ml = max(ml, (uint32_t)__shfl_xor(ml, o, WAVE));
+            uint32_t r = 0u;
+            for (uint32_t j = 0; j < ml; ++j) {
+                const int src = (head + (int)j) & (WAVE - 1);
+                Canon cj;
+                if constexpr (KB == 4) {
+                    cj.hi = (uint64_t)(uint32_t)__shfl((uint32_t)(ck.hi >> 32), src, WAVE) << 32;
+                    cj.lo = 0ull;
+                } else {
+                    cj.hi = __shfl(ck.hi, src, WAVE);
+                    cj.lo = (KB == 16) ? __shfl(ck.lo, src, WAVE) : 0ull;
+                }
+                const bool before = canon_less(cj, ck) || (cj.hi == ck.hi && cj.lo == ck.lo && j < i);
+                if (j < el && before) ++r;
+            }
+            if (act) {
+                KT::store(w.keys[0], (size_t)eb + r, raw_key<KB>(k, w.kind));
+                if constexpr (PAY) w.pay[0][eb + r] = pv;
+            }
+            done = end;
+        }
+    }
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        st_keys += __shfl_xor(st_keys, o, WAVE);
+        st_segs += __shfl_xor(st_segs, o, WAVE);
+    }
+    if (lane == 0 && st_segs) {
+        atomicAdd(&ctl->small_keys, st_keys);
+        atomicAdd(&ctl->small_segs, st_segs);
     }
 }
 
