@@ -1352,14 +1352,79 @@ __device__ __forceinline__ void lds_passes(FinishLds<KB, BT, ITEMS, PAY> &S, Can
     }
 }
 
+// Packs sub-arrays of at most 64 elements into the lanes of one wave.  Lane
+// l describes sub-array l by its length len (0: none).  For each group of
+// whole sub-arrays that fits into 64 lanes, in order, every lane calls
+// fn(l, i, head, act, el, ml): the sub-array l of the element it carries,
+// the element's index i there, the lane holding element 0 (head), whether
+// it carries an element at all (act), the sub-array's length el and the
+// longest length of the group (ml, the same in every lane).
+template <class F>
+__device__ __forceinline__ void wave_pack(uint32_t len, F &&fn) {
+    const int lane = lane_id();
+    uint32_t incl = len;  // sub-array l owns elements [incl - len, incl)
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o, WAVE);
+        if (lane >= o) incl += y;
+    }
+    const uint32_t total = __builtin_amdgcn_readlane(incl, WAVE - 1);
+    for (uint32_t done = 0u; done < total;) {
+        // the sub-arrays that end within the next 64 elements (a leading
+        // run of lanes, as incl never decreases); the one holding element
+        // `done` is always among them, since none exceeds 64 elements
+        const uint64_t fits = __ballot(incl <= done + WAVE);
+        const int last = 63 - __builtin_clzll(fits);
+        const uint32_t end = __builtin_amdgcn_readlane(incl, last);
+        const uint32_t q = done + (uint32_t)lane;
+        // sub-array of element q: the number of sub-arrays that end at or before q
+        int l = 0;
+#pragma unroll
+        for (int step = WAVE / 2; step > 0; step >>= 1)
+            if ((uint32_t)__shfl(incl, l + step - 1, WAVE) <= q) l += step;
+        const uint32_t el = __shfl(len, l, WAVE);
+        const uint32_t i = q - ((uint32_t)__shfl(incl, l, WAVE) - el);
+        const bool act = q < end;
+        uint32_t ml = act ? el : 0u;
+#pragma unroll
+        for (int o = 1; o < WAVE; o <<= 1) ml = max(ml, (uint32_t)__shfl_xor(ml, o, WAVE));
+        fn(l, i, (lane - (int)i) & (WAVE - 1), act, el, ml);
+        done = end;
+    }
+}
+
+// Place of element i among the el elements of its sub-array (held by lanes
+// head .. head + el - 1, keys ck): the number of elements that come before
+// it in the stable order, smaller or equal and earlier.  Every lane of the
+// wave takes part (ml: the longest sub-array of the wave's group).
+template <int KB>
+__device__ __forceinline__ uint32_t pack_rank(Canon ck, uint32_t i, uint32_t el, int head, uint32_t ml) {
+    uint32_t r = 0u;
+    for (uint32_t j = 0; j < ml; ++j) {
+        const int src = (head + (int)j) & (WAVE - 1);
+        Canon cj;
+        if constexpr (KB == 4) {
+            cj.hi = (uint64_t)(uint32_t)__shfl((uint32_t)(ck.hi >> 32), src, WAVE) << 32;
+            cj.lo = 0ull;
+        } else {
+            cj.hi = __shfl(ck.hi, src, WAVE);
+            cj.lo = (KB == 16) ? __shfl(ck.lo, src, WAVE) : 0ull;
+        }
+        const bool before = canon_less(cj, ck) || (cj.hi == ck.hi && cj.lo == ck.lo && j < i);
+        if (j < el && before) ++r;
+    }
+    return r;
+}
+
 // The segment in S is sorted stably by its bits [0, pe]: keys equal on them
 // form runs, each in input order, still to be ordered by the bits after pe
-// (the recursion on sub-arrays, done in LDS).  Each run of up to 64 keys is
-// ranked by one wave: a key's new place is the number of run members that
-// are smaller, or equal and earlier.  Returns true, with nothing of a longer
-// run moved, if some run is longer than 64 keys.
+// (the recursion on sub-arrays, done in LDS).  Runs of up to 64 keys are
+// ranked inside one wave, as many packed into its lanes at once as fit: a
+// key's new place is the number of run members that are smaller on the
+// leading nb bits, or equal there and earlier.  Returns true, with nothing
+// of a longer run moved, if some run is longer than 64 keys.
 template <int KB, int BT, int ITEMS, bool PAY>
-__device__ bool fix_runs(FinishLds<KB, BT, ITEMS, PAY> &S, int pe, uint32_t len) {
+__device__ bool fix_runs(FinishLds<KB, BT, ITEMS, PAY> &S, int pe, uint32_t len, int nb) {
     using KT = KeyT<KB>;
     using V = typename KT::V;
     constexpr int NW = BT / WAVE;
@@ -1388,34 +1453,39 @@ __device__ bool fix_runs(FinishLds<KB, BT, ITEMS, PAY> &S, int pe, uint32_t len)
     for (uint32_t p = threadIdx.x; p < len; p += BT)
         if (is_start(p)) list[at++] = (uint16_t)p;
     __syncthreads();
-    for (uint32_t r = wv; r < nruns; r += NW) {
-        const uint32_t s0 = list[r];
-        const uint32_t e = s0 + (uint32_t)lane;
-        const Canon ks = KT::canon(S.keys[s0]);
-        V k = KT::zero();
-        bool in = false;
-        if (e < len) {
-            k = S.keys[e];
-            in = canon_eq_under(KT::canon(k), ks, pm);
+    const Canon km = canon_lead_mask(nb);
+    for (uint32_t r0 = (uint32_t)wv * WAVE; r0 < nruns; r0 += NW * WAVE) {
+        // lane l: run r0 + l, its start and its length (a walk over the keys
+        // equal to the first; a key past the run differs from it however
+        // another wave may be permuting that key's own run)
+        uint32_t s0 = 0u, L = 0u;
+        if (r0 + (uint32_t)lane < nruns) {
+            s0 = list[r0 + lane];
+            const Canon ks = KT::canon(S.keys[s0]);
+            L = 2u;  // a run start has an equal successor
+            while (L <= (uint32_t)WAVE && s0 + L < len && canon_eq_under(KT::canon(S.keys[s0 + L]), ks, pm)) ++L;
+            if (L > (uint32_t)WAVE) {
+                S.long_run = 1u;  // left in place for the passes over every varying bit
+                L = 0u;
+            }
         }
-        const unsigned long long m = __ballot(in);
-        const uint32_t L = (~m == 0ull) ? 64u : (uint32_t)__builtin_ctzll(~m);
-        if (L == 64u && s0 + 64u < len && canon_eq_under(KT::canon(S.keys[s0 + 64u]), ks, pm)) {
-            if (lane == 0) S.long_run = 1u;
-            continue;
-        }
-        const Canon kc = KT::canon(k);
-        uint32_t rank = 0;
-        for (uint32_t q = 0; q < L; ++q) {
-            const Canon c = KT::canon(S.keys[s0 + q]);
-            rank += (canon_less(c, kc) || (q < (uint32_t)lane && !canon_less(kc, c))) ? 1u : 0u;
-        }
-        uint32_t pv = 0;
-        if (PAY && (uint32_t)lane < L) pv = S.pay[e];
-        if ((uint32_t)lane < L) {
-            S.keys[s0 + rank] = k;
-            if (PAY) S.pay[s0 + rank] = pv;
-        }
+        wave_pack(L, [&](int l, uint32_t i, int head, bool act, uint32_t el, uint32_t ml) {
+            const uint32_t s = __shfl(s0, l, WAVE);
+            V k = KT::zero();
+            uint32_t pv = 0u;
+            if (act) {
+                k = S.keys[s + i];
+                if (PAY) pv = S.pay[s + i];
+            }
+            Canon ck = KT::canon(k);
+            ck.hi &= km.hi;
+            ck.lo &= km.lo;
+            const uint32_t r = pack_rank<KB>(ck, i, el, head, ml);
+            if (act) {
+                S.keys[s + r] = k;
+                if (PAY) S.pay[s + r] = pv;
+            }
+        });
     }
     __syncthreads();
     const bool lng = S.long_run != 0u;
@@ -1514,7 +1584,7 @@ void k_finish(Work w, int cls) {
             const int f2 = first_set_from(diff, min(fb + 8, NB), NB);
             const int pe = (f2 >= NB) ? lb : min(lb, f2 + 7);
             lds_passes<KB, BT, ITEMS, PAY>(S, diff, bitpos, pe, len);
-            if (pe < lb && fix_runs<KB, BT, ITEMS, PAY>(S, pe, len))
+            if (pe < lb && fix_runs<KB, BT, ITEMS, PAY>(S, pe, len, NB))
                 lds_passes<KB, BT, ITEMS, PAY>(S, diff, bitpos, lb, len);
         }
         fin_store_keys<KB, BT>(w.keys[0], fe.begin, (size_t)fe.begin + len, S.keys, w.kind);
@@ -1563,31 +1633,8 @@ __global__ __launch_bounds__(THREADS) void k_finish_small(Work w) {
             st_keys += len;
             ++st_segs;
         }
-        // inclusive prefix of the lengths: entry l owns keys [incl - len, incl)
-        uint32_t incl = len;
-#pragma unroll
-        for (int o = 1; o < WAVE; o <<= 1) {
-            const uint32_t y = __shfl_up(incl, o, WAVE);
-            if (lane >= o) incl += y;
-        }
-        const uint32_t total = __builtin_amdgcn_readlane(incl, WAVE - 1);
-        for (uint32_t done = 0u; done < total;) {
-            // the entries that end within the next 64 keys (a leading run of
-            // lanes, as incl never decreases); the one holding key `done`
-            // is always among them, since no entry exceeds 64 keys
-            const uint64_t fits = __ballot(incl <= done + WAVE);
-            const int last = 63 - __builtin_clzll(fits);
-            const uint32_t end = __builtin_amdgcn_readlane(incl, last);
-            const uint32_t q = done + (uint32_t)lane;
-            const bool act = q < end;
-            // entry of key q: the number of entries that end at or before q
-            int l = 0;
-#pragma unroll
-            for (int step = WAVE / 2; step > 0; step >>= 1)
-                if ((uint32_t)__shfl(incl, l + step - 1, WAVE) <= q) l += step;
-            const uint32_t eb = __shfl(b, l, WAVE), el = __shfl(len, l, WAVE), ep = __shfl(par, l, WAVE);
-            const uint32_t i = q - ((uint32_t)__shfl(incl, l, WAVE) - el);  // index inside the sub-array
-            const int head = (lane - (int)i) & (WAVE - 1);
+        wave_pack(len, [&](int l, uint32_t i, int head, bool act, uint32_t el, uint32_t ml) {
+            const uint32_t eb = __shfl(b, l, WAVE), ep = __shfl(par, l, WAVE);
             V k = KT::zero();
             uint32_t pv = 0u;
             if (act) {
@@ -1597,30 +1644,12 @@ __global__ __launch_bounds__(THREADS) void k_finish_small(Work w) {
             Canon ck = KT::canon(k);
             ck.hi &= km.hi;
             ck.lo &= km.lo;
-            // longest sub-array of this group: the rank loop's trip count
-            uint32_t ml = act ? el : 0u;
-#pragma unroll
-            for (int o = 1; o < WAVE; o <<= 1) ml = max(ml, (uint32_t)__shfl_xor(ml, o, WAVE));
-            uint32_t r = 0u;
-            for (uint32_t j = 0; j < ml; ++j) {
-                const int src = (head + (int)j) & (WAVE - 1);
-                Canon cj;
-                if constexpr (KB == 4) {
-                    cj.hi = (uint64_t)(uint32_t)__shfl((uint32_t)(ck.hi >> 32), src, WAVE) << 32;
-                    cj.lo = 0ull;
-                } else {
-                    cj.hi = __shfl(ck.hi, src, WAVE);
-                    cj.lo = (KB == 16) ? __shfl(ck.lo, src, WAVE) : 0ull;
-                }
-                const bool before = canon_less(cj, ck) || (cj.hi == ck.hi && cj.lo == ck.lo && j < i);
-                if (j < el && before) ++r;
-            }
+            const uint32_t r = pack_rank<KB>(ck, i, el, head, ml);
             if (act) {
                 KT::store(w.keys[0], (size_t)eb + r, raw_key<KB>(k, w.kind));
                 if constexpr (PAY) w.pay[0][eb + r] = pv;
             }
-            done = end;
-        }
+        });
     }
 #pragma unroll
     for (int o = 1; o < WAVE; o <<= 1) {

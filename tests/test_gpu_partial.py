@@ -57,3 +57,28 @@ def test_wide_keys_partial(kb):
     keys = workloads.u64_zipf(n, 8, 1 << 10, 1.1) if kb == 8 else workloads.str16(n, 9, 6)
     for nbits in (8, 20, 48, 64, 8 * kb):
         check_partial(keys, min(nbits, 8 * kb), finish_max=200)
+
+
+@pytest.mark.parametrize("kb,nbits", [(8, 48), (8, 33), (16, 72), (16, 100)])
+def test_partial_ties_inside_finish(kb, nbits):
+    """One sub-array finished on chip whose keys vary over many leading bits,
+    in groups that agree on all nbits leading bits and differ after them:
+    the tied runs left by the on-chip digit passes must be ordered by the
+    leading nbits bits only, equal keys there keeping input order."""
+    rng = np.random.default_rng(nbits)
+    n = 4001
+    pool = rng.integers(0, 1 << 63, (250, kb // 8), dtype=np.uint64)
+    rows = pool[rng.integers(0, 250, n)]
+    # bits from nbits on are noise
+    noise = rng.integers(0, 1 << 63, (n, kb // 8), dtype=np.uint64)
+    lead = nbits
+    for wd in range(kb // 8):
+        hi_bits = min(max(lead - 64 * wd, 0), 64)
+        keep = np.uint64(0) if hi_bits == 0 else np.uint64(((1 << 64) - 1) ^ ((1 << (64 - hi_bits)) - 1))
+        rows[:, wd] = (rows[:, wd] & keep) | (noise[:, wd] & ~keep)
+    if kb == 8:
+        keys = rows[:, 0].copy()
+    else:
+        keys = rows.astype(">u8").view(np.uint8).reshape(n, 16).copy()
+    check_partial(keys, nbits)
+    check_partial(keys, nbits, finish_max=64)
