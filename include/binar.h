@@ -241,6 +241,25 @@ int binar_sort_strings(const uint8_t *bytes, uint64_t nbytes, const uint32_t *of
                        uint32_t *payload, void *stream, void *workspace, size_t workspace_bytes);
 size_t binar_strings_workspace_bytes(uint64_t n);
 
+/* In-place sort (sections "Space Analysis" and "Algorithm": the partition
+ * works inside the caller's array, with extra space that does not grow with
+ * the keys' size).  Same result as binar_sort_ex on one array: stable, keys
+ * (device, n * key_bytes) and payload (device, n, or NULL) are permuted in
+ * their own buffers.  No scratch copy of the keys exists: each pass sorts
+ * every tile of a segment by its digit in on-chip memory, writes it back
+ * over itself, and then moves every key to its place by following the
+ * cycles of the pass's permutation.  The workspace holds only per-segment
+ * and per-tile tables, 2 bits per key and a segment map (see
+ * binar_inplace_workspace_bytes: about a sixth of the data for 4-byte keys
+ * with payload, against twice the data for binar_sort_ex).
+ * params: digit_bits must be 0 or 8, tile_keys 0 or 4096, offsets 0 or 1
+ * (else BINAR_EINVAL); finish_max is raised to at least 256; key_bits and
+ * key_kind as for binar_sort_ex.  Asynchronous on stream; binar_stats_read
+ * reads its counters.  workspace may be NULL (pool). */
+int binar_sort_inplace(void *keys, uint32_t key_bytes, uint64_t n, uint32_t *payload, const binar_params *params,
+                       void *stream, void *workspace, size_t workspace_bytes);
+size_t binar_inplace_workspace_bytes(uint32_t key_bytes, uint64_t n, int has_payload, const binar_params *params);
+
 /* Static description of a status code. */
 const char *binar_strerror(int status);
 

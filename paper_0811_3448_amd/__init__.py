@@ -24,6 +24,8 @@ from .binar import (  # noqa: F401
     resolve_params,
     set_default_params,
     sort,
+    sort_inplace,
+    inplace_workspace_bytes,
     sort_segmented,
     sort_strings,
     stats,

@@ -73,6 +73,9 @@ def _load():
     L.binar_sort_strings.restype = i32
     L.binar_strings_workspace_bytes.argtypes = [u64]
     L.binar_strings_workspace_bytes.restype = sz
+    L.binar_sort_inplace.argtypes = [vp, u32, u64, vp, P, vp, vp, sz]
+    L.binar_inplace_workspace_bytes.argtypes = [u32, u64, i32, P]
+    L.binar_inplace_workspace_bytes.restype = sz
     L.binar_last_error.argtypes = []
     L.binar_last_error.restype = ctypes.c_char_p
     for f in ("binar_sort", "binar_sort_async", "binar_sort_segmented", "binar_sort_ex",
@@ -261,6 +264,26 @@ def sort_segmented(keys, seg_offsets, payload=None, stream=None, workspace: Work
     _check(lib.binar_sort_ex(_dev_ptr(keys), kb, n, _dev_ptr(payload), _dev_ptr(seg_offsets), nseg, pp,
                              _stream_ptr(stream), ws[0], ws[1]))
     return keys
+
+
+def sort_inplace(keys, payload=None, stream=None, workspace: Workspace | None = None,
+                 params: Params | None = None, key_kind: int | None = None):
+    """Stable sort like sort(), with no scratch copy of the keys: the passes
+    permute inside keys and payload themselves.  params: digit_bits 0/8,
+    tile_keys 0/4096, offsets 0/1.  Returns keys."""
+    _check_tensors(keys, payload)
+    params = key_kind_of(keys, params, key_kind)
+    kb = key_bytes_of(keys)
+    ws = (None, 0) if workspace is None else (workspace.ptr, workspace.nbytes)
+    pp = None if params is None else ctypes.byref(params.c())
+    _check(lib.binar_sort_inplace(_dev_ptr(keys), kb, keys.shape[0], _dev_ptr(payload), pp,
+                                  _stream_ptr(stream), ws[0], ws[1]))
+    return keys
+
+
+def inplace_workspace_bytes(key_bytes: int, n: int, has_payload: bool, params: Params | None = None) -> int:
+    pp = None if params is None else ctypes.byref(params.c())
+    return int(lib.binar_inplace_workspace_bytes(key_bytes, n, 1 if has_payload else 0, pp))
 
 
 def strings_workspace_bytes(n: int) -> int:

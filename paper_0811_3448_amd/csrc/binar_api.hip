@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "binar.h"
+#include "binar_inplace.h"
 #include "binar_kernels.h"
 #include "binar_strings.h"
 
@@ -97,11 +98,13 @@ struct Resolved {
     uint32_t kb, k, tile, T, nbits, kind;
     bool pay;
     bool lookback;
+    bool inplace = false;
 };
 
 struct Layout {
     size_t ctl, list[2], counts[2], bases[2], andor[2], desc[2], pcnt, status, fin[NCLASS], fin_small, cpy, keys_b,
-        pay_b, total;
+        pay_b, segmap, state, total;
+    uint32_t nmap, nstate;  // in place: segment-map entries and state words
     uint32_t max_big, max_tiles, max_fin[NCLASS], fin_cap[NCLASS], max_small, max_cpy;
 };
 
@@ -180,8 +183,10 @@ Layout make_layout(const Resolved &r, uint64_t n) {
     L.pcnt = take((size_t)L.max_tiles * R * 4);
     L.status = take(r.lookback ? (size_t)L.max_tiles * R * 4 : 0);
     // sub-arrays of 2 .. SMALL_MAX keys go to the small list, longer ones up
-    // to T to the smallest LDS class that holds them
-    L.max_small = (r.T >= 2u) ? (uint32_t)(n / 2ull + 1ull) : 0u;
+    // to T to the smallest LDS class that holds them; in place, only the
+    // caller's array can be listed there (small children of a pass are
+    // ranked from its count table)
+    L.max_small = (r.T >= 2u) ? (r.inplace ? 1u : (uint32_t)(n / 2ull + 1ull)) : 0u;
     L.fin_small = take((size_t)L.max_small * sizeof(FinEntry));
     uint32_t prev = SMALL_MAX;
     for (int c = 0; c < NCLASS; ++c) {
@@ -192,10 +197,14 @@ Layout make_layout(const Resolved &r, uint64_t n) {
     }
     // copy-back runs: each is bounded by a child that is not finished (two
     // or more keys) or by its parent's end
-    L.max_cpy = (uint32_t)(n / 2 + L.max_big + 2);
+    L.max_cpy = r.inplace ? 1u : (uint32_t)(n / 2 + L.max_big + 2);
     L.cpy = take((size_t)L.max_cpy * sizeof(CopyEntry));
-    L.keys_b = take((size_t)n * r.kb);
-    L.pay_b = take(r.pay ? (size_t)n * 4 : 0);
+    L.keys_b = take(r.inplace ? 0 : (size_t)n * r.kb);
+    L.pay_b = take((r.pay && !r.inplace) ? (size_t)n * 4 : 0);
+    L.nmap = r.inplace ? (uint32_t)(n / IP_GRANULE + 2) : 0u;
+    L.nstate = r.inplace ? (uint32_t)(n / 16 + 2) : 0u;
+    L.segmap = take((size_t)L.nmap * sizeof(uint2));
+    L.state = take((size_t)L.nstate * 4);
     L.total = off;
     return L;
 }
@@ -296,11 +305,12 @@ Work make_work(const Layout &L, const Resolved &r, char *ws, void *keys, uint32_
     w.tile_keys = r.tile;
     w.nbits = r.nbits;
     w.kind = r.kind;
+    w.inplace = r.inplace ? 1u : 0u;
     w.n_total = n_total;
     w.keys[0] = keys;
-    w.keys[1] = ws + L.keys_b;
+    w.keys[1] = r.inplace ? nullptr : ws + L.keys_b;
     w.pay[0] = pay;
-    w.pay[1] = r.pay ? reinterpret_cast<uint32_t *>(ws + L.pay_b) : nullptr;
+    w.pay[1] = (r.pay && !r.inplace) ? reinterpret_cast<uint32_t *>(ws + L.pay_b) : nullptr;
     return w;
 }
 
@@ -508,6 +518,133 @@ int run(void *keys, uint32_t kb, uint64_t n, uint32_t *payload, const uint32_t *
     (void)hipGetLastError();  // a stale error of earlier, unrelated HIP calls is not ours
     const Work w = make_work(L, r, static_cast<char *>(ws), keys, payload, (uint32_t)n);
     return dispatch(r, w, L, seg_off, seg_off ? nseg : 1u, (uint32_t)n, st);
+}
+
+// ------------------------------------------------------------ in place
+// Parameters of the in-place passes: 8-bit digits, 4096-key tiles, chunked
+// piece prefixes, and T at least a segment-map granule.
+int resolve_inplace(uint32_t kb, bool pay, const binar_params *p, Resolved *r) {
+    if (p && ((p->digit_bits && p->digit_bits != (uint32_t)IP_K) || (p->tile_keys && p->tile_keys != IP_TILE) ||
+              p->offsets == 2))
+        return BINAR_EINVAL;
+    binar_params d;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        d = g_defaults[kb_index(kb)][pay ? 1 : 0];
+    }
+    d.digit_bits = IP_K;
+    d.tile_keys = IP_TILE;
+    d.offsets = 1;
+    binar_params q = p ? *p : binar_params{};
+    q.digit_bits = 0;
+    q.tile_keys = 0;
+    q.offsets = 0;
+    if (int rc = resolve_over(kb, pay, d, p ? &q : nullptr, r)) return rc;
+    r->T = std::max(r->T, IP_GRANULE);
+    r->inplace = true;
+    return BINAR_OK;
+}
+
+template <int KB, bool PAY>
+int enqueue_inplace(Work w, const Layout &L, char *ws, uint32_t n, hipStream_t st) {
+    constexpr int R = 1 << IP_K;
+    const int passes = ((int)w.nbits + IP_K - 1) / IP_K;
+    IpMaps m;
+    m.dist = reinterpret_cast<int32_t *>(w.pcnt);  // each row replaces the piece prefix it came from
+    m.segmap = reinterpret_cast<uint2 *>(ws + L.segmap);
+    m.state = reinterpret_cast<uint32_t *>(ws + L.state);
+    {
+        Timed tm(st, "k_reset", -1);
+        hipLaunchKernelGGL(k_reset, dim3(1), dim3(THREADS), 0, st, w.ctl);
+    }
+    {
+        Timed tm(st, "k_init", -1);
+        hipLaunchKernelGGL(k_init<R>, dim3(1), dim3(THREADS), 0, st, w, nullptr, 1u, n, n);
+    }
+    // the local sort and the digit count share one grid: it fixes the pieces
+    const uint32_t lg = grid_for(k_local<KB, PAY>, L.max_tiles, IP_BT);
+    w.chunk_grid = lg;
+    const uint32_t pg = std::max(1u, std::min(L.max_big, 1024u));
+    const uint32_t qg = std::max(1u, std::min(L.max_big * (uint32_t)(R / 32), 2048u));
+    const uint32_t cg = grid_for(k_cycle<KB, PAY>, L.max_tiles);
+    const uint32_t clr = grid_for(k_ip_clear, (L.nstate + THREADS - 1) / THREADS);
+    const uint32_t spg = grid_for(k_small_pairs<KB, PAY>, (L.max_big * (uint32_t)R + THREADS - 1) / THREADS);
+    for (int j = 0; j < passes; ++j) {
+        const int Lc = j & 1;
+        {
+            Timed tm(st, "k_hist", j);
+            hipLaunchKernelGGL((k_hist<KB, IP_K, false, HIST_BT>), dim3(lg), dim3(HIST_BT), 0, st, w, Lc);
+        }
+        {
+            Timed tm(st, "k_pscan", j);
+            hipLaunchKernelGGL((k_pscan<IP_K>), dim3(qg), dim3(THREADS), 0, st, w, Lc);
+        }
+        {
+            Timed tm(st, "k_plan", j);
+            hipLaunchKernelGGL((k_plan<KB, IP_K>), dim3(pg), dim3(THREADS), 0, st, w, Lc, j);
+        }
+        {
+            Timed tm(st, "k_ip_clear", j);
+            hipLaunchKernelGGL(k_ip_clear, dim3(clr), dim3(THREADS), 0, st, m, L.nstate, L.nmap);
+        }
+        {
+            Timed tm(st, "k_local", j);
+            hipLaunchKernelGGL((k_local<KB, PAY>), dim3(lg), dim3(IP_BT), 0, st, w, Lc, m);
+        }
+        {
+            Timed tm(st, "k_cycle", j);
+            hipLaunchKernelGGL((k_cycle<KB, PAY>), dim3(cg), dim3(THREADS), 0, st, w, Lc, m);
+        }
+        {
+            Timed tm(st, "k_small_pairs", j);
+            hipLaunchKernelGGL((k_small_pairs<KB, PAY>), dim3(spg), dim3(THREADS), 0, st, w, Lc);
+        }
+    }
+    {
+        Timed tm(st, "k_finish_small", -1);
+        hipLaunchKernelGGL((k_finish_small<KB, PAY>), dim3(1), dim3(THREADS), 0, st, w);
+    }
+    launch_finish<KB, PAY, 0>(w, L, st);
+    launch_finish<KB, PAY, 1>(w, L, st);
+    launch_finish<KB, PAY, 2>(w, L, st);
+    launch_finish<KB, PAY, 3>(w, L, st);
+    BINAR_HIP_TRY(hipGetLastError());
+    return BINAR_OK;
+}
+
+int run_inplace(void *keys, uint32_t kb, uint64_t n, uint32_t *payload, const binar_params *params, hipStream_t st,
+                void *ws, size_t ws_bytes) {
+    if (!valid_kb(kb)) return BINAR_EINVAL;
+    if (n > BINAR_MAX_KEYS) return BINAR_ERANGE;
+    if (n < 2) return BINAR_OK;  // base case: nothing to order
+    if (int rc = check_buffers(keys, kb, payload)) return rc;
+    Resolved r;
+    int rc = resolve_inplace(kb, payload != nullptr, params, &r);
+    if (rc) return rc;
+    const Layout L = make_layout(r, n);
+    int dev = 0;
+    BINAR_HIP_TRY(hipGetDevice(&dev));
+    if (ws) {
+        if (ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & (ALIGN - 1))) return BINAR_ENOMEM;
+    } else {
+        rc = pool_get(dev, L.total, &ws);
+        if (rc) return rc;
+    }
+    note_ws(dev, ws);
+    (void)hipGetLastError();
+    char *b = static_cast<char *>(ws);
+    const Work w = make_work(L, r, b, keys, payload, (uint32_t)n);
+    switch (kb) {
+        case 4:
+            return payload ? enqueue_inplace<4, true>(w, L, b, (uint32_t)n, st)
+                           : enqueue_inplace<4, false>(w, L, b, (uint32_t)n, st);
+        case 8:
+            return payload ? enqueue_inplace<8, true>(w, L, b, (uint32_t)n, st)
+                           : enqueue_inplace<8, false>(w, L, b, (uint32_t)n, st);
+        default:
+            return payload ? enqueue_inplace<16, true>(w, L, b, (uint32_t)n, st)
+                           : enqueue_inplace<16, false>(w, L, b, (uint32_t)n, st);
+    }
 }
 
 // ------------------------------------------------------------ strings
@@ -895,6 +1032,20 @@ int binar_profile_read(binar_launch_time *out, uint32_t cap, uint32_t *count) {
 }
 
 const char *binar_last_error(void) { return binar::t_err; }
+
+int binar_sort_inplace(void *keys, uint32_t key_bytes, uint64_t n, uint32_t *payload, const binar_params *params,
+                       void *stream, void *workspace, size_t workspace_bytes) {
+    return binar::run_inplace(keys, key_bytes, n, payload, params, static_cast<hipStream_t>(stream), workspace,
+                              workspace_bytes);
+}
+
+size_t binar_inplace_workspace_bytes(uint32_t key_bytes, uint64_t n, int has_payload, const binar_params *params) {
+    using namespace binar;
+    if (!valid_kb(key_bytes) || n > BINAR_MAX_KEYS) return 0;
+    Resolved r;
+    if (resolve_inplace(key_bytes, has_payload != 0, params, &r)) return 0;
+    return make_layout(r, n).total;
+}
 
 size_t binar_strings_workspace_bytes(uint64_t n) {
     if (n > BINAR_MAX_KEYS) return 0;

@@ -1,0 +1,414 @@
+// In-place passes: no scratch copy of the keys.
+//
+// The paper's partition works inside the array it is given, and the space it
+// needs beyond the array does not grow with the data (section "Space
+// Analysis").  Its exchange of two keys is not stable; the passes here keep
+// the stable order of the scatter passes and still move the keys only within
+// the caller's buffer.  One pass over the live segments of list L:
+//
+//   k_local   every tile of a segment that is partitioned sorts itself
+//             stably by the pass digit in LDS and is written back over
+//             itself.  Keys of one digit in one tile then sit in one run
+//             whose place after the pass is known (bucket base + the
+//             digit's count in the segment's earlier tiles), so every key
+//             of the run moves by the same distance: one int32 per (tile,
+//             digit), in a table that takes the place of the piece prefixes
+//             it was computed from.
+//   k_cycle   applies the permutation  i -> i + dist[tile(i)][digit(key i)]
+//             by following its cycles: each lane carries one key to its
+//             place, picks up the key found there and carries that one on.
+//             Two state bits per position make every key picked up exactly
+//             once and every place written exactly once.
+//   k_small_pairs  children of 2..SMALL_MAX keys, read straight from the
+//             pass's count table and ranked inside a wave (no list).
+//
+// The extra memory is the per-segment and per-tile tables, 2 bits per key and
+// 8 bytes per IP_GRANULE positions: a small fraction of the data.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "binar_kernels.h"
+
+namespace binar {
+
+constexpr uint32_t IP_GRANULE = 256;     // positions per entry of the segment map
+constexpr uint32_t IP_NONE = 0xFFFFFFFFu;
+constexpr int IP_K = 8;                  // digit bits of the in-place passes
+constexpr int IP_BT = 512, IP_ITEMS = 8;  // one tile = 4096 keys
+constexpr uint32_t IP_TILE = IP_BT * IP_ITEMS;
+
+// Where position i lies: the segment map holds, for every granule of
+// IP_GRANULE positions, the live segment (list slot) holding its first
+// position and the one holding its last.  A live segment is longer than a
+// granule (T >= IP_GRANULE), so it holds the first or the last position of
+// every granule it touches.
+struct IpMaps {
+    int32_t *dist;      // [tile][R]: aliases the piece-prefix table
+    uint2 *segmap;      // [granule]: (slot holding the first position, slot holding the last)
+    uint32_t *state;    // 2 bits per position: 1 = claimed, 2 = its key was picked up
+};
+
+// Clear the state bits and the segment map before a pass.
+__global__ __launch_bounds__(THREADS) void k_ip_clear(IpMaps m, uint32_t nstate, uint32_t nmap) {
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nstate; i += stride) m.state[i] = 0u;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nmap; i += stride)
+        m.segmap[i] = make_uint2(IP_NONE, IP_NONE);
+}
+
+template <int KB, bool PAY>
+struct LocalLds {
+    using V = typename KeyT<KB>::V;
+    static constexpr int R = 1 << IP_K;
+    static constexpr int NW = IP_BT / WAVE;
+    V keys[IP_TILE];
+    uint32_t pay[PAY ? IP_TILE : 1];
+    alignas(8) uint32_t tbl[NW][2 * R];
+    uint32_t wh[NW][R];
+    uint32_t run[R];   // place after the pass of the next key of digit d in this piece
+    uint32_t tmp[NW];
+};
+
+// The tiles of list L are cut into gridDim.x chunks exactly as in k_hist, so
+// the piece prefixes line up; the grid must be the one k_hist ran with.
+template <int KB, bool PAY>
+__global__ __launch_bounds__(IP_BT) void k_local(Work w, int L, IpMaps m) {
+    using KT = KeyT<KB>;
+    using V = typename KT::V;
+    constexpr int R = 1 << IP_K;
+    constexpr int NW = IP_BT / WAVE;
+    __shared__ LocalLds<KB, PAY> S;
+    Ctl *ctl = w.ctl;
+    if (ctl->error | ctl->overflow) return;
+    const unsigned long long lc = ctl->list_ctr[L];
+    const uint32_t nslots = (uint32_t)(lc >> 32), ntiles = (uint32_t)lc;
+    if (ntiles == 0) return;
+    const uint32_t per = (ntiles + gridDim.x - 1) / gridDim.x;
+    const uint32_t t0 = blockIdx.x * per, t1 = min(ntiles, t0 + per);
+    if (t0 >= t1) return;
+    const int wv = threadIdx.x / WAVE, lane = lane_id();
+    for (int i = threadIdx.x; i < NW * R; i += IP_BT) (&S.wh[0][0])[i] = 0u;
+    for (int i = threadIdx.x; i < NW * 2 * R; i += IP_BT) (&S.tbl[0][0])[i] = 0u;
+    __syncthreads();
+
+    uint32_t t = t0;
+    uint32_t slot = uni(find_slot(w.list[L], nslots, t));
+    SegEntry seg = uni(w.list[L][slot]);
+    uint32_t seg_end = uni(seg_tile_end(w.list[L], slot, nslots, ntiles));
+    bool entered = false;
+    const uint32_t ebase = (uint32_t)wv * IP_ITEMS * WAVE + (uint32_t)lane;
+    while (t < t1) {
+        if (!entered) {
+            if (((seg.info >> 16) & SEG_SKIP) || ((seg.info >> 8) & 1u)) {
+                // not partitioned this pass (an odd parity never occurs in place)
+                if ((seg.info >> 8) & 1u) {
+                    if (threadIdx.x == 0) atomicOr(&ctl->error, ERR_INTERNAL);
+                }
+                t = seg_end;
+                if (t >= t1) break;
+                ++slot;
+                seg = uni(w.list[L][slot]);
+                seg_end = uni(seg_tile_end(w.list[L], slot, nslots, ntiles));
+                continue;
+            }
+            if (threadIdx.x < R)
+                S.run[threadIdx.x] = w.bases[L][(size_t)slot * R + threadIdx.x] + w.pcnt[(size_t)t * R + threadIdx.x];
+            entered = true;
+            __syncthreads();
+        }
+        const uint32_t bitpos = seg.info & 0xFFu;
+        const int wbits = min(IP_K, (int)w.nbits - (int)bitpos);
+        const uint32_t off = (t - seg.tile_start) * IP_TILE;
+        const uint32_t tlen = min(IP_TILE, seg.len - off);
+        const uint32_t tb = seg.begin + off;
+        if ((size_t)tb + tlen > w.n_total) {
+            if (threadIdx.x == 0) atomicOr(&ctl->error, ERR_INTERNAL);
+            break;
+        }
+        V key[IP_ITEMS];
+        uint32_t pay[IP_ITEMS], dg[IP_ITEMS], rnk[IP_ITEMS];
+#pragma unroll
+        for (int j = 0; j < IP_ITEMS; ++j) {
+            const uint32_t e = ebase + j * WAVE;
+            key[j] = (e < tlen) ? ld_key<KB>(w.keys[0], (size_t)tb + e, w.kind) : KT::zero();
+            pay[j] = (PAY && e < tlen) ? w.pay[0][tb + e] : 0u;
+            dg[j] = KT::digit(key[j], bitpos, wbits);
+        }
+        wave_rank<R, RANK_GROUP, IP_ITEMS, false>(dg, ebase, tlen, &S.tbl[wv][0], &S.wh[wv][0], rnk);
+        __syncthreads();
+        uint32_t tcnt = 0;
+        if (threadIdx.x < R) {
+#pragma unroll
+            for (int q = 0; q < NW; ++q) tcnt += S.wh[q][threadIdx.x];
+        }
+        uint32_t tot;
+        const uint32_t dstart = block_excl_scan<IP_BT>(tcnt, S.tmp, &tot);  // every thread: it holds barriers
+        if (threadIdx.x < R) {
+            uint32_t acc = dstart;
+#pragma unroll
+            for (int q = 0; q < NW; ++q) {
+                const uint32_t x = S.wh[q][threadIdx.x];
+                S.wh[q][threadIdx.x] = acc;
+                acc += x;
+            }
+            // a key of digit d at tile position dstart + r goes to run + r;
+            // this row was read (as the piece prefix) only by this block
+            const uint32_t run = S.run[threadIdx.x];
+            m.dist[(size_t)t * R + threadIdx.x] = (int32_t)(run - (tb + dstart));
+            S.run[threadIdx.x] = run + tcnt;
+        }
+        // the segment map for the granules this tile touches
+        {
+            const uint32_t g0 = tb / IP_GRANULE, g1 = (tb + tlen - 1) / IP_GRANULE;
+            const uint32_t sb = seg.begin, se = seg.begin + seg.len;
+            for (uint32_t g = g0 + threadIdx.x; g <= g1; g += IP_BT) {
+                const uint32_t first = g * IP_GRANULE, last = first + IP_GRANULE - 1;
+                if (first >= sb && first < se) m.segmap[g].x = slot;
+                if (last >= sb && last < se) m.segmap[g].y = slot;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < IP_ITEMS; ++j) {
+            const uint32_t e = ebase + j * WAVE;
+            if (e < tlen) {
+                const uint32_t pos = S.wh[wv][dg[j]] + rnk[j];
+                S.keys[pos] = key[j];
+                if (PAY) S.pay[pos] = pay[j];
+            }
+        }
+        __syncthreads();
+        for (int i = lane; i < R; i += WAVE) S.wh[wv][i] = 0u;
+        // every key of the tile is in LDS: write it back over the tile
+#pragma unroll
+        for (int j = 0; j < IP_ITEMS; ++j) {
+            const uint32_t p = j * IP_BT + threadIdx.x;
+            if (p < tlen) {
+                KT::store(w.keys[0], (size_t)tb + p, raw_key<KB>(S.keys[p], w.kind));
+                if (PAY) w.pay[0][tb + p] = S.pay[p];
+            }
+        }
+        __syncthreads();
+        ++t;
+        if (t == seg_end && t < t1) {
+            ++slot;
+            seg = uni(w.list[L][slot]);
+            seg_end = uni(seg_tile_end(w.list[L], slot, nslots, ntiles));
+            entered = false;
+        }
+    }
+}
+
+// Position i's state bits: the word and the shift.
+__device__ __forceinline__ uint32_t *ip_word(uint32_t *state, uint32_t i) { return state + (i >> 4); }
+__device__ __forceinline__ uint32_t ip_shift(uint32_t i) { return (i & 15u) * 2u; }
+
+// The place after the pass of the key now at position i (value v, sorting
+// view): IP_NONE if i lies in no live segment of the map (never expected).
+template <int KB>
+__device__ __forceinline__ uint32_t ip_dest(const Work &w, int L, const IpMaps &m, uint32_t i,
+                                            typename KeyT<KB>::V v) {
+    const uint2 gm = m.segmap[i / IP_GRANULE];
+    uint32_t slot = IP_NONE;
+    SegEntry seg{};
+    if (gm.x != IP_NONE) {
+        seg = w.list[L][gm.x];
+        if (i >= seg.begin && i - seg.begin < seg.len) slot = gm.x;
+    }
+    if (slot == IP_NONE && gm.y != IP_NONE) {
+        seg = w.list[L][gm.y];
+        if (i >= seg.begin && i - seg.begin < seg.len) slot = gm.y;
+    }
+    if (slot == IP_NONE) return IP_NONE;
+    const uint32_t bitpos = seg.info & 0xFFu;
+    const int wbits = min(IP_K, (int)w.nbits - (int)bitpos);
+    const uint32_t t = seg.tile_start + (i - seg.begin) / IP_TILE;
+    const uint32_t d = KeyT<KB>::digit(v, bitpos, wbits);
+    const uint32_t k = (uint32_t)((int32_t)i + m.dist[(size_t)t * (1u << IP_K) + d]);
+    // the place lies in the same segment
+    if (k < seg.begin || k - seg.begin >= seg.len) return IP_NONE;
+    return k;
+}
+
+// Every position of every partitioned segment of list L starts a chain once
+// (a lane whose start is already claimed simply takes the next one).  Per
+// step, every lane has a target: a new start, or the place of the key it
+// carries.  It claims the target; a winner picks up the key there (then marks
+// it picked up) and, if it carried one, puts that one down; a loser that
+// carries waits until the target's key has been picked up, puts its key down
+// and stops.  The claims of a step and the pick-ups of its winners come
+// before any wait of the step in every wave, so a wait only ever depends on
+// a pick-up that follows a claim with no wait in between: none waits for
+// long.
+template <int KB, bool PAY>
+__global__ __launch_bounds__(THREADS) void k_cycle(Work w, int L, IpMaps m) {
+    using KT = KeyT<KB>;
+    using V = typename KT::V;
+    Ctl *ctl = w.ctl;
+    if (ctl->error | ctl->overflow) return;
+    const unsigned long long lc = ctl->list_ctr[L];
+    const uint32_t nslots = (uint32_t)(lc >> 32), ntiles = (uint32_t)lc;
+    if (ntiles == 0) return;
+    const int lane = lane_id();
+    const uint32_t wave_id = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    const uint32_t nwaves = gridDim.x * (blockDim.x / WAVE);
+
+    bool carry = false;
+    V x = KT::zero();          // carried key (as stored)
+    uint32_t px = 0u;
+    uint32_t src = 0u;         // where the carried key was picked up
+    uint32_t t = wave_id;      // this wave's tile of start positions
+    uint32_t cur = 0u, tb = 0u, tlen = 0u;  // next start inside it
+    bool tiles_left = true;
+    unsigned long long st_steps = 0ull;
+    for (;;) {
+        // the next tile with start positions left, if lanes are idle
+        while (tiles_left && cur >= tlen) {
+            if (t >= ntiles) {
+                tiles_left = false;
+                break;
+            }
+            const uint32_t slot = uni(find_slot(w.list[L], nslots, t));
+            const SegEntry seg = uni(w.list[L][slot]);
+            if (((seg.info >> 16) & SEG_SKIP) || ((seg.info >> 8) & 1u)) {
+                t += nwaves;
+                continue;
+            }
+            const uint32_t off = (t - seg.tile_start) * IP_TILE;
+            tb = seg.begin + off;
+            tlen = min(IP_TILE, seg.len - off);
+            cur = 0u;
+            t += nwaves;
+        }
+        const bool idle = !carry;
+        const uint64_t idle_m = __ballot(idle);
+        if (!tiles_left && idle_m == ~0ull) break;  // no start left, nothing carried
+        // targets: idle lanes take consecutive start positions
+        uint32_t tgt = IP_NONE;
+        if (idle) {
+            const uint32_t r = cur + lanes_below(idle_m);
+            if (tiles_left && r < tlen) tgt = tb + r;
+        } else {
+            tgt = ip_dest<KB>(w, L, m, src, w.kind ? KT::enc(x, w.kind) : x);
+            if (tgt == IP_NONE || tgt >= w.n_total) {
+                atomicOr(&ctl->error, ERR_INTERNAL);
+                carry = false;
+            }
+        }
+        if (tiles_left) cur += (uint32_t)__builtin_popcountll(idle_m);
+        // claim
+        bool won = false;
+        if (tgt != IP_NONE && tgt < w.n_total) {
+            const uint32_t sh = ip_shift(tgt);
+            const uint32_t old = __hip_atomic_fetch_or(ip_word(m.state, tgt), 1u << sh, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+            won = ((old >> sh) & 1u) == 0u;
+        }
+        // winners pick up the key at the target, mark it, put theirs down
+        if (won) {
+            const V y = KT::load(w.keys[0], tgt);
+            const uint32_t py = PAY ? w.pay[0][tgt] : 0u;
+            // the pick-up is complete before the mark is visible
+            __hip_atomic_fetch_or(ip_word(m.state, tgt), 2u << ip_shift(tgt), __ATOMIC_SEQ_CST,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+            if (carry) {
+                KT::store(w.keys[0], tgt, x);
+                if (PAY) w.pay[0][tgt] = px;
+                ++st_steps;
+            }
+            x = y;
+            px = py;
+            src = tgt;
+            carry = true;
+        }
+        __builtin_amdgcn_wave_barrier();
+        // carrying losers: the target's key is (being) picked up by its claimer
+        if (carry && !won && tgt != IP_NONE) {
+            const uint32_t sh = ip_shift(tgt);
+            uint32_t spins = 0;
+            while (((__hip_atomic_load(ip_word(m.state, tgt), __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT) >> sh) &
+                    2u) == 0u &&
+                   spins < SPIN_LIMIT) {
+                __builtin_amdgcn_s_sleep(1);
+                ++spins;
+            }
+            if (spins >= SPIN_LIMIT) atomicOr(&ctl->error, ERR_INTERNAL);
+            KT::store(w.keys[0], tgt, x);
+            if (PAY) w.pay[0][tgt] = px;
+            ++st_steps;
+            carry = false;
+        }
+    }
+    (void)st_steps;
+}
+
+// Children of 2..SMALL_MAX keys of the segments partitioned with list L,
+// taken from its count and base tables: each wave takes 64 (segment, digit)
+// pairs at a time and ranks the small ones, packed into its lanes, in place.
+template <int KB, bool PAY>
+__global__ __launch_bounds__(THREADS) void k_small_pairs(Work w, int L) {
+    using KT = KeyT<KB>;
+    using V = typename KT::V;
+    constexpr int R = 1 << IP_K;
+    Ctl *ctl = w.ctl;
+    if (ctl->error | ctl->overflow) return;
+    const unsigned long long lc = ctl->list_ctr[L];
+    const uint32_t nslots = (uint32_t)(lc >> 32);
+    if (nslots == 0) return;
+    const uint32_t npairs = nslots * (uint32_t)R;
+    const int lane = lane_id();
+    const uint32_t wave_id = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    const uint32_t nwaves = gridDim.x * (blockDim.x / WAVE);
+    const Canon km = canon_lead_mask((int)w.nbits);
+    unsigned long long st_keys = 0ull, st_segs = 0ull;
+    for (uint32_t e0 = wave_id * WAVE; e0 < npairs; e0 += nwaves * WAVE) {
+        // 64 pairs never straddle two segments: R is a multiple of 64
+        const uint32_t s = e0 / R;
+        const SegEntry seg = uni(w.list[L][s]);
+        if (((seg.info >> 16) & SEG_SKIP) || ((seg.info >> 8) & 1u)) continue;
+        const uint32_t e = e0 + lane;
+        const uint32_t c = w.counts[L][e];
+        uint32_t b = 0u, len = 0u;
+        if (c >= 2u && c <= SMALL_MAX) {
+            b = w.bases[L][e];
+            len = c;
+            if (b < seg.begin || b - seg.begin + c > seg.len) {
+                atomicOr(&ctl->error, ERR_INTERNAL);
+                len = 0u;
+            } else {
+                st_keys += len;
+                ++st_segs;
+            }
+        }
+        wave_pack(len, [&](int l, uint32_t i, int head, bool act, uint32_t el, uint32_t ml) {
+            const uint32_t eb = __shfl(b, l, WAVE);
+            V k = KT::zero();
+            uint32_t pv = 0u;
+            if (act) {
+                k = ld_key<KB>(w.keys[0], (size_t)eb + i, w.kind);
+                if constexpr (PAY) pv = w.pay[0][eb + i];
+            }
+            Canon ck = KT::canon(k);
+            ck.hi &= km.hi;
+            ck.lo &= km.lo;
+            const uint32_t r = pack_rank<KB>(ck, i, el, head, ml);
+            if (act) {
+                KT::store(w.keys[0], (size_t)eb + r, raw_key<KB>(k, w.kind));
+                if constexpr (PAY) w.pay[0][eb + r] = pv;
+            }
+        });
+    }
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        st_keys += __shfl_xor(st_keys, o, WAVE);
+        st_segs += __shfl_xor(st_segs, o, WAVE);
+    }
+    if (lane == 0 && st_segs) {
+        atomicAdd(&ctl->small_keys, st_keys);
+        atomicAdd(&ctl->small_segs, st_segs);
+    }
+}
+
+}  // namespace binar

@@ -126,6 +126,7 @@ struct Work {
     uint32_t chunk_grid;           // blocks of k_hist / k_scatter: fixes the pieces
     uint32_t nbits;                // leading key bits to sort by (the key width unless limited)
     uint32_t kind;                 // KIND_*: how key bits are ordered; loads apply enc, stores dec
+    uint32_t inplace;              // passes permute inside A (no B); small children are not listed
     void *keys[2];                 // A, B
     uint32_t *pay[2];              // A, B (NULL without payload)
 };
@@ -726,15 +727,17 @@ __global__ __launch_bounds__(THREADS) void k_plan(Work w, int L, int pass) {
         int cat = -1;
         uint32_t cb = 0;
         bool done = false;
-        const uint32_t child_parity = parity ^ 1u;
+        const uint32_t child_parity = w.inplace ? 0u : parity ^ 1u;
         if (c != 0u) {
             cb = (uint32_t)first_set_from(diff, bitpos + wbits, NB);
             done = (c == 1u) || (cb >= (uint32_t)NB);
             w.bases[L][(size_t)s * R + d] = seg.begin + excl;
             if (!done) cat = (c <= w.finish_max) ? fin_class(w, c) : NCLASS;
+            // in place, small children are ranked straight from this table
+            if (w.inplace && cat == CAT_SMALL) cat = -1;
         }
         st_moved += seg.len;
-        if (parity == 0u) {
+        if (parity == 0u && !w.inplace) {
             // finished children land in B: one copy-back range per run of
             // adjacent finished children (empty digits do not break a run)
             s_state[d] = (c == 0u) ? 0u : (done ? 1u : 2u);
