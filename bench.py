@@ -480,6 +480,8 @@ def main() -> int:
     ap.add_argument("--str-log2", type=int, default=24, help="str_var workload: log2 of the string count")
     ap.add_argument("--lin-dump", default="", help="linearity workload: write n,ms,passes CSV here")
     ap.add_argument("--serve-budget-gib", type=int, default=32)
+    ap.add_argument("--inplace", action="store_true",
+                    help="single-array workloads: the in-place variant (no scratch copy of the keys)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -522,16 +524,22 @@ def main() -> int:
     K, W = args.steps, args.warmup
     bufs = [(pristine.clone(), None if pay0 is None else pay0.clone()) for _ in range(K + W)]
     params, source = choose_params(binar, args, kb, has_pay, n, batched=False)
+    if args.inplace:
+        # fixed pass shape (8-bit digits, 4096-key tiles, chunk prefixes)
+        params, source = binar.Params(finish_max=args.finish_max), "in-place pass shape"
     if name.startswith("f32"):
         # IEEE-754 keys: same kernels, keys read through the order-preserving view
         params = binar.Params(**{**vars(params), "key_kind": binar.KEY_FLOAT})
-    ws = binar.Workspace(binar.workspace_bytes(kb, n, has_pay, 1, params), device=dev)
+    pp_ws_bytes = binar.workspace_bytes(kb, n, has_pay, 1, params)
+    ip_ws_bytes = binar.inplace_workspace_bytes(kb, n, has_pay, params)
+    ws = binar.Workspace(ip_ws_bytes if args.inplace else pp_ws_bytes, device=dev)
+    sort_fn = binar.sort_inplace if args.inplace else binar.sort
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
 
     print("bench: warmup %d" % W, file=sys.stderr, flush=True)
     for i in range(W):
-        binar.sort(bufs[i][0], bufs[i][1], workspace=ws, params=params)
+        sort_fn(bufs[i][0], bufs[i][1], workspace=ws, params=params)
     torch.cuda.synchronize()
     st = binar.stats(ws)
     if st["status"] != 0:
@@ -546,7 +554,7 @@ def main() -> int:
     t0 = time.perf_counter()
     ev0.record(stream)
     for i in range(W, W + K):
-        binar.sort(bufs[i][0], bufs[i][1], workspace=ws, params=params)
+        sort_fn(bufs[i][0], bufs[i][1], workspace=ws, params=params)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -573,8 +581,14 @@ def main() -> int:
 
     # algorithmic bytes per sort, per kernel kind (exact counters from the device)
     pb = 4 if has_pay else 0
-    per_kernel = {"k_hist": sum(kb * x for x in st["hist_keys"]),
-                  "k_scatter": sum(2 * (kb + pb) * x for x in st["moved"])}
+    per_kernel = {"k_hist": sum(kb * x for x in st["hist_keys"])}
+    if args.inplace:
+        # each partitioned key is read and written by the tile sort, then
+        # picked up and put down once by the cycle walk
+        per_kernel["k_local"] = sum(2 * (kb + pb) * x for x in st["moved"])
+        per_kernel["k_cycle"] = sum(2 * (kb + pb) * x for x in st["moved"])
+    else:
+        per_kernel["k_scatter"] = sum(2 * (kb + pb) * x for x in st["moved"])
     for c in range(4):
         per_kernel["k_finish%d" % c] = 2 * (kb + pb) * st["finish_class_keys"][c]
     per_kernel["k_finish_small"] = 2 * (kb + pb) * st["finish_small_keys"]
@@ -597,8 +611,9 @@ def main() -> int:
     # the LDS finish as the last stage
     per_pass = []
     for j in range(16):
-        ms = sum(m for nm, ps, m in launches if ps == j and nm in ("k_hist", "k_pscan", "k_plan", "k_scatter")) / K
-        b = kb * st["hist_keys"][j] + 2 * (kb + pb) * st["moved"][j]
+        ms = sum(m for nm, ps, m in launches if ps == j and nm in (
+            "k_hist", "k_pscan", "k_plan", "k_scatter", "k_ip_clear", "k_local", "k_cycle", "k_small_pairs")) / K
+        b = kb * st["hist_keys"][j] + 2 * (kb + pb) * st["moved"][j] * (2 if args.inplace else 1)
         if b == 0:
             continue
         per_pass.append({"pass": j, "ms": round(ms, 4), "bytes": int(b),
@@ -626,9 +641,13 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f32" if name.startswith("f32") else ("u32" if kb == 4 else ("u64" if kb == 8 else "u8x16")),
         "data": "synthetic",
-        "config": {"workload": "%s: %s" % (name, desc), "n": n, "key_bytes": kb, "payload_bytes": pb,
+        "config": {"workload": "%s%s: %s" % (name, " in place" if args.inplace else "", desc), "n": n,
+                   "key_bytes": kb, "payload_bytes": pb, "variant": "in place" if args.inplace else "ping-pong",
                    **describe_params(binar, kb, has_pay, params, source),
                    "parallelism": "single GPU"},
+        "workspace_bytes": {"used": int(ip_ws_bytes if args.inplace else pp_ws_bytes),
+                            "in_place": int(ip_ws_bytes), "ping_pong": int(pp_ws_bytes),
+                            "data": int((kb + pb) * n)},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(dom, name),
@@ -643,6 +662,9 @@ def main() -> int:
         "moved_per_pass": [x for x in st["moved"] if x],
         "wall_s": round(wall, 4),
     }
+    if args.inplace:
+        result["config"].update(digit_bits=8, tile_keys=4096, offsets="chunk prefixes",
+                                finish_max=max(result["config"]["finish_max"], 256))
     if not args.no_cpu_baseline:
         print("bench: CPU oracle sample", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(keys_np, args.cpu_sample_log2)

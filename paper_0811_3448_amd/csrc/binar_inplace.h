@@ -310,8 +310,16 @@ __global__ __launch_bounds__(THREADS) void k_cycle(Work w, int L, IpMaps m) {
         if (won) {
             const V y = KT::load(w.keys[0], tgt);
             const uint32_t py = PAY ? w.pay[0][tgt] : 0u;
-            // the pick-up is complete before the mark is visible
-            __hip_atomic_fetch_or(ip_word(m.state, tgt), 2u << ip_shift(tgt), __ATOMIC_SEQ_CST,
+            // the pick-up has returned before the mark is issued: a put-down
+            // that waits for the mark can no longer change what was picked
+            // up.  (Device-scope release/acquire orderings would also write
+            // back and invalidate the L2 of the wave's XCD at every step;
+            // nothing else needs ordering here, since no key is read after
+            // it has been written within one walk.)
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            __builtin_amdgcn_s_waitcnt(0);
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            __hip_atomic_fetch_or(ip_word(m.state, tgt), 2u << ip_shift(tgt), __ATOMIC_RELAXED,
                                   __HIP_MEMORY_SCOPE_AGENT);
             if (carry) {
                 KT::store(w.keys[0], tgt, x);
@@ -328,7 +336,7 @@ __global__ __launch_bounds__(THREADS) void k_cycle(Work w, int L, IpMaps m) {
         if (carry && !won && tgt != IP_NONE) {
             const uint32_t sh = ip_shift(tgt);
             uint32_t spins = 0;
-            while (((__hip_atomic_load(ip_word(m.state, tgt), __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT) >> sh) &
+            while (((__hip_atomic_load(ip_word(m.state, tgt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> sh) &
                     2u) == 0u &&
                    spins < SPIN_LIMIT) {
                 __builtin_amdgcn_s_sleep(1);
