@@ -249,7 +249,7 @@ size_t binar_strings_workspace_bytes(uint64_t n);
  * every tile of a segment by its digit in on-chip memory, writes it back
  * over itself, and then moves every key to its place by following the
  * cycles of the pass's permutation.  The workspace holds only per-segment
- * and per-tile tables, 2 bits per key and a segment map (see
+ * and per-tile tables, 1 bit per key and a segment map (see
  * binar_inplace_workspace_bytes: about a sixth of the data for 4-byte keys
  * with payload, against twice the data for binar_sort_ex).
  * params: digit_bits must be 0 or 8, tile_keys 0 or 4096, offsets 0 or 1

@@ -202,8 +202,8 @@ Layout make_layout(const Resolved &r, uint64_t n) {
     L.keys_b = take(r.inplace ? 0 : (size_t)n * r.kb);
     L.pay_b = take((r.pay && !r.inplace) ? (size_t)n * 4 : 0);
     L.nmap = r.inplace ? (uint32_t)(n / IP_GRANULE + 2) : 0u;
-    L.nstate = r.inplace ? (uint32_t)(n / 16 + 2) : 0u;
-    L.segmap = take((size_t)L.nmap * sizeof(uint2));
+    L.nstate = r.inplace ? (uint32_t)(n / 32 + 2) : 0u;
+    L.segmap = take((size_t)L.nmap * sizeof(uint4));
     L.state = take((size_t)L.nstate * 4);
     L.total = off;
     return L;
@@ -551,7 +551,7 @@ int enqueue_inplace(Work w, const Layout &L, char *ws, uint32_t n, hipStream_t s
     const int passes = ((int)w.nbits + IP_K - 1) / IP_K;
     IpMaps m;
     m.dist = reinterpret_cast<int32_t *>(w.pcnt);  // each row replaces the piece prefix it came from
-    m.segmap = reinterpret_cast<uint2 *>(ws + L.segmap);
+    m.segmap = reinterpret_cast<uint4 *>(ws + L.segmap);
     m.state = reinterpret_cast<uint32_t *>(ws + L.state);
     {
         Timed tm(st, "k_reset", -1);
@@ -622,6 +622,7 @@ int run_inplace(void *keys, uint32_t kb, uint64_t n, uint32_t *payload, const bi
     int rc = resolve_inplace(kb, payload != nullptr, params, &r);
     if (rc) return rc;
     const Layout L = make_layout(r, n);
+    if (L.max_tiles >= (1u << 24)) return BINAR_ERANGE;  // tile numbers share a word with the bit position
     int dev = 0;
     BINAR_HIP_TRY(hipGetDevice(&dev));
     if (ws) {

@@ -17,13 +17,13 @@
 //   k_cycle   applies the permutation  i -> i + dist[tile(i)][digit(key i)]
 //             by following its cycles: each lane carries one key to its
 //             place, picks up the key found there and carries that one on.
-//             Two state bits per position make every key picked up exactly
+//             One claim bit per position makes every key picked up exactly
 //             once and every place written exactly once.
 //   k_small_pairs  children of 2..SMALL_MAX keys, read straight from the
 //             pass's count table and ranked inside a wave (no list).
 //
-// The extra memory is the per-segment and per-tile tables, 2 bits per key and
-// 8 bytes per IP_GRANULE positions: a small fraction of the data.
+// The extra memory is the per-segment and per-tile tables, 1 bit per key and
+// 16 bytes per IP_GRANULE positions: a small fraction of the data.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -40,14 +40,15 @@ constexpr int IP_BT = 512, IP_ITEMS = 8;  // one tile = 4096 keys
 constexpr uint32_t IP_TILE = IP_BT * IP_ITEMS;
 
 // Where position i lies: the segment map holds, for every granule of
-// IP_GRANULE positions, the live segment (list slot) holding its first
-// position and the one holding its last.  A live segment is longer than a
-// granule (T >= IP_GRANULE), so it holds the first or the last position of
-// every granule it touches.
+// IP_GRANULE positions, the live segment holding its first position and the
+// one holding its last, each as (begin, first tile | bit position << 24).  A
+// live segment is longer than a granule (T >= IP_GRANULE), so it holds the
+// first or the last position of every granule it touches, and a position at
+// or after the begin of the second lies in the second.
 struct IpMaps {
     int32_t *dist;      // [tile][R]: aliases the piece-prefix table
-    uint2 *segmap;      // [granule]: (slot holding the first position, slot holding the last)
-    uint32_t *state;    // 2 bits per position: 1 = claimed, 2 = its key was picked up
+    uint4 *segmap;      // [granule]: (first-position segment, last-position segment)
+    uint32_t *state;    // 1 bit per position: claimed (its first claimer took the key it held)
 };
 
 // Clear the state bits and the segment map before a pass.
@@ -55,7 +56,7 @@ __global__ __launch_bounds__(THREADS) void k_ip_clear(IpMaps m, uint32_t nstate,
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nstate; i += stride) m.state[i] = 0u;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nmap; i += stride)
-        m.segmap[i] = make_uint2(IP_NONE, IP_NONE);
+        m.segmap[i] = make_uint4(IP_NONE, 0u, IP_NONE, 0u);
 }
 
 template <int KB, bool PAY>
@@ -163,10 +164,17 @@ __global__ __launch_bounds__(IP_BT) void k_local(Work w, int L, IpMaps m) {
         {
             const uint32_t g0 = tb / IP_GRANULE, g1 = (tb + tlen - 1) / IP_GRANULE;
             const uint32_t sb = seg.begin, se = seg.begin + seg.len;
+            const uint32_t inf = seg.tile_start | (bitpos << 24);
             for (uint32_t g = g0 + threadIdx.x; g <= g1; g += IP_BT) {
                 const uint32_t first = g * IP_GRANULE, last = first + IP_GRANULE - 1;
-                if (first >= sb && first < se) m.segmap[g].x = slot;
-                if (last >= sb && last < se) m.segmap[g].y = slot;
+                if (first >= sb && first < se) {
+                    m.segmap[g].x = sb;
+                    m.segmap[g].y = inf;
+                }
+                if (last >= sb && last < se) {
+                    m.segmap[g].z = sb;
+                    m.segmap[g].w = inf;
+                }
             }
         }
         __syncthreads();
@@ -201,47 +209,53 @@ __global__ __launch_bounds__(IP_BT) void k_local(Work w, int L, IpMaps m) {
     }
 }
 
-// Position i's state bits: the word and the shift.
-__device__ __forceinline__ uint32_t *ip_word(uint32_t *state, uint32_t i) { return state + (i >> 4); }
-__device__ __forceinline__ uint32_t ip_shift(uint32_t i) { return (i & 15u) * 2u; }
+// Position i's claim bit: the word and the bit.
+__device__ __forceinline__ uint32_t *ip_word(uint32_t *state, uint32_t i) { return state + (i >> 5); }
+__device__ __forceinline__ uint32_t ip_bit(uint32_t i) { return 1u << (i & 31u); }
+
+// A hardware wait for every memory operation the wave has issued (the
+// compiler keeps memory operations on their side of the signal fences).
+__device__ __forceinline__ void ip_wait_all() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
 
 // The place after the pass of the key now at position i (value v, sorting
 // view): IP_NONE if i lies in no live segment of the map (never expected).
 template <int KB>
-__device__ __forceinline__ uint32_t ip_dest(const Work &w, int L, const IpMaps &m, uint32_t i,
-                                            typename KeyT<KB>::V v) {
-    const uint2 gm = m.segmap[i / IP_GRANULE];
-    uint32_t slot = IP_NONE;
-    SegEntry seg{};
-    if (gm.x != IP_NONE) {
-        seg = w.list[L][gm.x];
-        if (i >= seg.begin && i - seg.begin < seg.len) slot = gm.x;
+__device__ __forceinline__ uint32_t ip_dest(const Work &w, const IpMaps &m, uint32_t i, typename KeyT<KB>::V v) {
+    const uint4 gm = m.segmap[i / IP_GRANULE];
+    uint32_t b, inf;
+    if (gm.z != IP_NONE && i >= gm.z) {
+        b = gm.z;
+        inf = gm.w;
+    } else if (gm.x != IP_NONE) {
+        b = gm.x;
+        inf = gm.y;
+    } else {
+        return IP_NONE;
     }
-    if (slot == IP_NONE && gm.y != IP_NONE) {
-        seg = w.list[L][gm.y];
-        if (i >= seg.begin && i - seg.begin < seg.len) slot = gm.y;
-    }
-    if (slot == IP_NONE) return IP_NONE;
-    const uint32_t bitpos = seg.info & 0xFFu;
+    const uint32_t bitpos = inf >> 24;
     const int wbits = min(IP_K, (int)w.nbits - (int)bitpos);
-    const uint32_t t = seg.tile_start + (i - seg.begin) / IP_TILE;
-    const uint32_t d = KeyT<KB>::digit(v, bitpos, wbits);
-    const uint32_t k = (uint32_t)((int32_t)i + m.dist[(size_t)t * (1u << IP_K) + d]);
-    // the place lies in the same segment
-    if (k < seg.begin || k - seg.begin >= seg.len) return IP_NONE;
-    return k;
+    const uint32_t t = (inf & 0xFFFFFFu) + (i - b) / IP_TILE;
+    const uint32_t d = KeyT<KB>::digit(v, (int)bitpos, wbits);
+    return (uint32_t)((int32_t)i + m.dist[(size_t)t * (1u << IP_K) + d]);
 }
 
-// Every position of every partitioned segment of list L starts a chain once
-// (a lane whose start is already claimed simply takes the next one).  Per
-// step, every lane has a target: a new start, or the place of the key it
-// carries.  It claims the target; a winner picks up the key there (then marks
-// it picked up) and, if it carried one, puts that one down; a loser that
-// carries waits until the target's key has been picked up, puts its key down
-// and stops.  The claims of a step and the pick-ups of its winners come
-// before any wait of the step in every wave, so a wait only ever depends on
-// a pick-up that follows a claim with no wait in between: none waits for
-// long.
+// Every position of every partitioned segment of list L starts a walk once
+// (unless a walk has claimed it already).  Per step, every lane has a
+// target: a new start, or the place of the key it carries.  It reads the
+// key at the target, waits for the read, then claims the target with one
+// atomic; after the claim has returned it puts its carried key (if any)
+// down there.  The first claimer of a place goes on with the key it read;
+// any other claimer's walk ends.  Why that is exact: every place is claimed
+// first exactly once, and the key its first claimer read is the one that
+// was there at the start -- a place is only written after its writer's claim
+// has returned, and every claim of a place but the first comes after the
+// first claim, which was issued after the first claimer's read had returned.
+// Each place receives its key once (from the unique carrier of that key),
+// and no lane ever waits for another.
 template <int KB, bool PAY>
 __global__ __launch_bounds__(THREADS) void k_cycle(Work w, int L, IpMaps m) {
     using KT = KeyT<KB>;
@@ -251,7 +265,6 @@ __global__ __launch_bounds__(THREADS) void k_cycle(Work w, int L, IpMaps m) {
     const unsigned long long lc = ctl->list_ctr[L];
     const uint32_t nslots = (uint32_t)(lc >> 32), ntiles = (uint32_t)lc;
     if (ntiles == 0) return;
-    const int lane = lane_id();
     const uint32_t wave_id = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
     const uint32_t nwaves = gridDim.x * (blockDim.x / WAVE);
 
@@ -259,12 +272,11 @@ __global__ __launch_bounds__(THREADS) void k_cycle(Work w, int L, IpMaps m) {
     V x = KT::zero();          // carried key (as stored)
     uint32_t px = 0u;
     uint32_t src = 0u;         // where the carried key was picked up
-    uint32_t t = wave_id;      // this wave's tile of start positions
-    uint32_t cur = 0u, tb = 0u, tlen = 0u;  // next start inside it
+    uint32_t t = wave_id;      // this wave's next tile of start positions
+    uint32_t cur = 0u, tb = 0u, tlen = 0u;  // next start inside the current one
     bool tiles_left = true;
-    unsigned long long st_steps = 0ull;
     for (;;) {
-        // the next tile with start positions left, if lanes are idle
+        // the next tile with start positions left
         while (tiles_left && cur >= tlen) {
             if (t >= ntiles) {
                 tiles_left = false;
@@ -285,71 +297,46 @@ __global__ __launch_bounds__(THREADS) void k_cycle(Work w, int L, IpMaps m) {
         const bool idle = !carry;
         const uint64_t idle_m = __ballot(idle);
         if (!tiles_left && idle_m == ~0ull) break;  // no start left, nothing carried
-        // targets: idle lanes take consecutive start positions
         uint32_t tgt = IP_NONE;
         if (idle) {
             const uint32_t r = cur + lanes_below(idle_m);
             if (tiles_left && r < tlen) tgt = tb + r;
         } else {
-            tgt = ip_dest<KB>(w, L, m, src, w.kind ? KT::enc(x, w.kind) : x);
+            tgt = ip_dest<KB>(w, m, src, w.kind ? KT::enc(x, w.kind) : x);
             if (tgt == IP_NONE || tgt >= w.n_total) {
                 atomicOr(&ctl->error, ERR_INTERNAL);
                 carry = false;
+                tgt = IP_NONE;
             }
         }
         if (tiles_left) cur += (uint32_t)__builtin_popcountll(idle_m);
-        // claim
-        bool won = false;
-        if (tgt != IP_NONE && tgt < w.n_total) {
-            const uint32_t sh = ip_shift(tgt);
-            const uint32_t old = __hip_atomic_fetch_or(ip_word(m.state, tgt), 1u << sh, __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_AGENT);
-            won = ((old >> sh) & 1u) == 0u;
+        // read the target (and, for a start, whether a walk has claimed it)
+        V y = KT::zero();
+        uint32_t py = 0u, claimed = 0u;
+        if (tgt != IP_NONE) {
+            y = KT::load(w.keys[0], tgt);
+            if (PAY) py = w.pay[0][tgt];
+            if (idle) claimed = __hip_atomic_load(ip_word(m.state, tgt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        // winners pick up the key at the target, mark it, put theirs down
+        ip_wait_all();
+        bool won = false;
+        if (tgt != IP_NONE && !(claimed & ip_bit(tgt))) {
+            const uint32_t old = __hip_atomic_fetch_or(ip_word(m.state, tgt), ip_bit(tgt), __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+            won = (old & ip_bit(tgt)) == 0u;
+        }
+        ip_wait_all();
+        if (carry) {
+            KT::store(w.keys[0], tgt, x);
+            if (PAY) w.pay[0][tgt] = px;
+        }
+        carry = won;
         if (won) {
-            const V y = KT::load(w.keys[0], tgt);
-            const uint32_t py = PAY ? w.pay[0][tgt] : 0u;
-            // the pick-up has returned before the mark is issued: a put-down
-            // that waits for the mark can no longer change what was picked
-            // up.  (Device-scope release/acquire orderings would also write
-            // back and invalidate the L2 of the wave's XCD at every step;
-            // nothing else needs ordering here, since no key is read after
-            // it has been written within one walk.)
-            __atomic_signal_fence(__ATOMIC_SEQ_CST);
-            __builtin_amdgcn_s_waitcnt(0);
-            __atomic_signal_fence(__ATOMIC_SEQ_CST);
-            __hip_atomic_fetch_or(ip_word(m.state, tgt), 2u << ip_shift(tgt), __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_AGENT);
-            if (carry) {
-                KT::store(w.keys[0], tgt, x);
-                if (PAY) w.pay[0][tgt] = px;
-                ++st_steps;
-            }
             x = y;
             px = py;
             src = tgt;
-            carry = true;
-        }
-        __builtin_amdgcn_wave_barrier();
-        // carrying losers: the target's key is (being) picked up by its claimer
-        if (carry && !won && tgt != IP_NONE) {
-            const uint32_t sh = ip_shift(tgt);
-            uint32_t spins = 0;
-            while (((__hip_atomic_load(ip_word(m.state, tgt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> sh) &
-                    2u) == 0u &&
-                   spins < SPIN_LIMIT) {
-                __builtin_amdgcn_s_sleep(1);
-                ++spins;
-            }
-            if (spins >= SPIN_LIMIT) atomicOr(&ctl->error, ERR_INTERNAL);
-            KT::store(w.keys[0], tgt, x);
-            if (PAY) w.pay[0][tgt] = px;
-            ++st_steps;
-            carry = false;
         }
     }
-    (void)st_steps;
 }
 
 // Children of 2..SMALL_MAX keys of the segments partitioned with list L,
