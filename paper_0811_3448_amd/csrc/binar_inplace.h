@@ -243,6 +243,37 @@ __device__ __forceinline__ uint32_t ip_dest(const Work &w, const IpMaps &m, uint
     return (uint32_t)((int32_t)i + m.dist[(size_t)t * (1u << IP_K) + d]);
 }
 
+// Claim bit `tgt` for every lane that wants it; true for the lane that
+// claims it first.  Neighbouring lanes whose bits share a state word (runs
+// of one digit move together, so they mostly do) are served by one atomic,
+// the OR of their bits, issued by the last lane of the run; inside the run,
+// lanes count as claiming in lane order.
+__device__ __forceinline__ bool ip_claim(uint32_t *state, uint32_t tgt, bool want) {
+    const int lane = lane_id();
+    const uint32_t wd = want ? (tgt >> 5) : IP_NONE;
+    const uint32_t prev = __shfl_up(wd, 1, WAVE);
+    const bool head = want && (lane == 0 || prev != wd);
+    const uint64_t heads = __ballot(head) | __ballot(!want);  // a lane that wants nothing is its own run
+    const int hd = 63 - __builtin_clzll(heads & (~0ull >> (63 - lane)));
+    uint32_t acc = want ? ip_bit(tgt) : 0u;
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        const uint32_t y = __shfl_up(acc, o, WAVE);
+        if (lane - o >= hd) acc |= y;
+    }
+    const uint64_t after = (lane == 63) ? 0ull : (heads & (~0ull << (lane + 1)));
+    const int last = after ? __builtin_ctzll(after) - 1 : 63;
+    uint32_t old = 0u;
+    if (want && lane == last)
+        old = __hip_atomic_fetch_or(state + (tgt >> 5), acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    old = __shfl(old, last, WAVE);
+    // two lanes of a run may want one bit (a start and a carried key's
+    // place): the earlier lane is its first claimer
+    const uint32_t before = __shfl_up(acc, 1, WAVE);
+    const uint32_t earlier = (lane > hd) ? before : 0u;
+    return want && ((old | earlier) & ip_bit(tgt)) == 0u;
+}
+
 // Every position of every partitioned segment of list L starts a walk once
 // (unless a walk has claimed it already).  Per step, every lane has a
 // target: a new start, or the place of the key it carries.  It reads the
@@ -319,12 +350,8 @@ __global__ __launch_bounds__(THREADS) void k_cycle(Work w, int L, IpMaps m) {
             if (idle) claimed = __hip_atomic_load(ip_word(m.state, tgt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         ip_wait_all();
-        bool won = false;
-        if (tgt != IP_NONE && !(claimed & ip_bit(tgt))) {
-            const uint32_t old = __hip_atomic_fetch_or(ip_word(m.state, tgt), ip_bit(tgt), __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_AGENT);
-            won = (old & ip_bit(tgt)) == 0u;
-        }
+        const bool want = tgt != IP_NONE && !(claimed & ip_bit(tgt));
+        const bool won = ip_claim(m.state, tgt, want);
         ip_wait_all();
         if (carry) {
             KT::store(w.keys[0], tgt, x);
