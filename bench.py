@@ -29,9 +29,14 @@ PROFILES = os.path.join(ROOT, "profiles")
 CSRC = os.path.join(ROOT, "paper_0811_3448_amd", "csrc")
 
 
+# the sources the fixed-width sort's kernels and launches are built from
+# (the string and in-place paths live in files of their own)
+TRAFFIC_SOURCES = ("binar_api.hip", "binar_keys.h", "binar_kernels.h")
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in sorted(os.listdir(CSRC)):
+    for f in TRAFFIC_SOURCES:
         with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(f.encode() + b"\0" + fh.read())
     return h.hexdigest()
