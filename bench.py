@@ -55,6 +55,28 @@ def measured_traffic(kernel: str, workload: str):
     return t.get("traffic_bytes_per_launch")
 
 
+def copy_ceiling(torch, dev, nbytes: int = 2 << 30, reps: int = 5):
+    """Achievable bandwidth on the day: a device-to-device copy of nbytes
+    (read + write), timed with HIP events; median of reps."""
+    src = torch.empty(nbytes, dtype=torch.uint8, device=dev).fill_(1)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    stream = torch.cuda.current_stream()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        dst.copy_(src)
+        e1.record(stream)
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ms = sorted(ts)[len(ts) // 2]
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"gbs": round(2 * nbytes / (ms * 1e-3) / 1e9, 1), "bytes_copied": nbytes, "ms": round(ms, 4),
+            "what": "2 GiB device-to-device copy (read + write bytes), median of %d" % reps}
+
+
 def cpu_baseline(keys_np, log2_sample: int):
     import numpy as np
     import oracle
@@ -670,6 +692,12 @@ def main() -> int:
     if args.inplace:
         result["config"].update(digit_bits=8, tile_keys=4096, offsets="chunk prefixes",
                                 finish_max=max(result["config"]["finish_max"], 256))
+    del bufs
+    torch.cuda.empty_cache()
+    cc = copy_ceiling(torch, dev)
+    result["copy_ceiling"] = cc
+    result["roofline"]["frac_of_copy"] = round(achieved / cc["gbs"], 4)
+    result["sort_roofline"]["frac_of_copy"] = round(total_bytes / (ms_per_step * 1e-3) / 1e9 / cc["gbs"], 4)
     if not args.no_cpu_baseline:
         print("bench: CPU oracle sample", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(keys_np, args.cpu_sample_log2)

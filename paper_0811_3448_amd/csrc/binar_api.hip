@@ -566,7 +566,7 @@ int enqueue_inplace(Work w, const Layout &L, char *ws, uint32_t n, hipStream_t s
     w.chunk_grid = lg;
     const uint32_t pg = std::max(1u, std::min(L.max_big, 1024u));
     const uint32_t qg = std::max(1u, std::min(L.max_big * (uint32_t)(R / 32), 2048u));
-    const uint32_t cg = grid_for(k_cycle<KB, PAY>, L.max_tiles);
+    const uint32_t cg = grid_for(k_cycle<KB, PAY, 2>, L.max_tiles);
     const uint32_t clr = grid_for(k_ip_clear, (L.nstate + THREADS - 1) / THREADS);
     const uint32_t spg = grid_for(k_small_pairs<KB, PAY>, (L.max_big * (uint32_t)R + THREADS - 1) / THREADS);
     for (int j = 0; j < passes; ++j) {
@@ -593,7 +593,7 @@ int enqueue_inplace(Work w, const Layout &L, char *ws, uint32_t n, hipStream_t s
         }
         {
             Timed tm(st, "k_cycle", j);
-            hipLaunchKernelGGL((k_cycle<KB, PAY>), dim3(cg), dim3(THREADS), 0, st, w, Lc, m);
+            hipLaunchKernelGGL((k_cycle<KB, PAY, 2>), dim3(cg), dim3(THREADS), 0, st, w, Lc, m);
         }
         {
             Timed tm(st, "k_small_pairs", j);

@@ -221,34 +221,19 @@ __device__ __forceinline__ void ip_wait_all() {
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-// The place after the pass of the key now at position i (value v, sorting
-// view): IP_NONE if i lies in no live segment of the map (never expected).
-template <int KB>
-__device__ __forceinline__ uint32_t ip_dest(const Work &w, const IpMaps &m, uint32_t i, typename KeyT<KB>::V v) {
-    const uint4 gm = m.segmap[i / IP_GRANULE];
-    uint32_t b, inf;
-    if (gm.z != IP_NONE && i >= gm.z) {
-        b = gm.z;
-        inf = gm.w;
-    } else if (gm.x != IP_NONE) {
-        b = gm.x;
-        inf = gm.y;
-    } else {
-        return IP_NONE;
-    }
-    const uint32_t bitpos = inf >> 24;
-    const int wbits = min(IP_K, (int)w.nbits - (int)bitpos);
-    const uint32_t t = (inf & 0xFFFFFFu) + (i - b) / IP_TILE;
-    const uint32_t d = KeyT<KB>::digit(v, (int)bitpos, wbits);
-    return (uint32_t)((int32_t)i + m.dist[(size_t)t * (1u << IP_K) + d]);
-}
+// Claim bit `tgt` for every lane that wants it; the lane that claims it
+// first wins.  Neighbouring lanes whose bits share a state word (runs of one
+// digit move together, so they mostly do) are served by one atomic, the OR of
+// their bits, issued by the last lane of the run; inside the run, lanes count
+// as claiming in lane order.  Split in two so that the atomics of several
+// walks per lane are in flight together: ip_claim_issue leaves the word's
+// old value in the issuing lane, ip_claim_won tells every lane its outcome.
+struct IpClaim {
+    uint32_t old, earlier;
+    int last;
+};
 
-// Claim bit `tgt` for every lane that wants it; true for the lane that
-// claims it first.  Neighbouring lanes whose bits share a state word (runs
-// of one digit move together, so they mostly do) are served by one atomic,
-// the OR of their bits, issued by the last lane of the run; inside the run,
-// lanes count as claiming in lane order.
-__device__ __forceinline__ bool ip_claim(uint32_t *state, uint32_t tgt, bool want) {
+__device__ __forceinline__ IpClaim ip_claim_issue(uint32_t *state, uint32_t tgt, bool want) {
     const int lane = lane_id();
     const uint32_t wd = want ? (tgt >> 5) : IP_NONE;
     const uint32_t prev = __shfl_up(wd, 1, WAVE);
@@ -262,35 +247,67 @@ __device__ __forceinline__ bool ip_claim(uint32_t *state, uint32_t tgt, bool wan
         if (lane - o >= hd) acc |= y;
     }
     const uint64_t after = (lane == 63) ? 0ull : (heads & (~0ull << (lane + 1)));
-    const int last = after ? __builtin_ctzll(after) - 1 : 63;
-    uint32_t old = 0u;
-    if (want && lane == last)
-        old = __hip_atomic_fetch_or(state + (tgt >> 5), acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    old = __shfl(old, last, WAVE);
+    IpClaim c;
+    c.last = after ? __builtin_ctzll(after) - 1 : 63;
     // two lanes of a run may want one bit (a start and a carried key's
     // place): the earlier lane is its first claimer
     const uint32_t before = __shfl_up(acc, 1, WAVE);
-    const uint32_t earlier = (lane > hd) ? before : 0u;
-    return want && ((old | earlier) & ip_bit(tgt)) == 0u;
+    c.earlier = (lane > hd) ? before : 0u;
+    c.old = 0u;
+    if (want && lane == c.last)
+        c.old = __hip_atomic_fetch_or(state + (tgt >> 5), acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return c;
+}
+
+__device__ __forceinline__ bool ip_claim_won(const IpClaim &c, uint32_t tgt, bool want) {
+    const uint32_t old = __shfl(c.old, c.last, WAVE);
+    return want && ((old | c.earlier) & ip_bit(tgt)) == 0u;
+}
+
+// Where position i lies, from the segment map entry gm of its granule: the
+// tile and the bit position of its segment (t = IP_NONE if the map has no
+// segment for it, never expected for a position of a partitioned segment).
+struct IpLoc {
+    uint32_t t, bitpos;
+};
+
+__device__ __forceinline__ IpLoc ip_loc(uint4 gm, uint32_t i) {
+    uint32_t b, inf;
+    if (gm.z != IP_NONE && i >= gm.z) {
+        b = gm.z;
+        inf = gm.w;
+    } else if (gm.x != IP_NONE) {
+        b = gm.x;
+        inf = gm.y;
+    } else {
+        return IpLoc{IP_NONE, 0u};
+    }
+    return IpLoc{(inf & 0xFFFFFFu) + (i - b) / IP_TILE, inf >> 24};
 }
 
 // Every position of every partitioned segment of list L starts a walk once
-// (unless a walk has claimed it already).  Per step, every lane has a
-// target: a new start, or the place of the key it carries.  It reads the
-// key at the target, waits for the read, then claims the target with one
-// atomic; after the claim has returned it puts its carried key (if any)
-// down there.  The first claimer of a place goes on with the key it read;
-// any other claimer's walk ends.  Why that is exact: every place is claimed
-// first exactly once, and the key its first claimer read is the one that
-// was there at the start -- a place is only written after its writer's claim
-// has returned, and every claim of a place but the first comes after the
-// first claim, which was issued after the first claimer's read had returned.
-// Each place receives its key once (from the unique carrier of that key),
-// and no lane ever waits for another.
-template <int KB, bool PAY>
+// (unless a walk has claimed it already).  Per step, every walk has a
+// target: a new start, or the place of the key it carries.  It reads the key
+// at the target, waits for the read, then claims the target; after the claim
+// has returned it puts its carried key (if any) down there.  The first
+// claimer of a place goes on with the key it read; any other claimer's walk
+// ends.  Why that is exact: every place is claimed first exactly once, and
+// the key its first claimer read is the one that was there at the start -- a
+// place is only written after its writer's claim has returned, and every
+// claim of a place but the first comes after the first claim, which was
+// issued after the first claimer's read had returned.  Each place receives
+// its key once (from the unique carrier of that key), and no lane ever waits
+// for another.
+//
+// Each lane runs NS walks side by side (their reads, claims and writes in
+// flight together), and the distance of a picked-up key is loaded right
+// after its claim, so a step waits for three memory round trips: distance,
+// read, claim.
+template <int KB, bool PAY, int NS>
 __global__ __launch_bounds__(THREADS) void k_cycle(Work w, int L, IpMaps m) {
     using KT = KeyT<KB>;
     using V = typename KT::V;
+    constexpr uint32_t R = 1u << IP_K;
     Ctl *ctl = w.ctl;
     if (ctl->error | ctl->overflow) return;
     const unsigned long long lc = ctl->list_ctr[L];
@@ -299,12 +316,19 @@ __global__ __launch_bounds__(THREADS) void k_cycle(Work w, int L, IpMaps m) {
     const uint32_t wave_id = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
     const uint32_t nwaves = gridDim.x * (blockDim.x / WAVE);
 
-    bool carry = false;
-    V x = KT::zero();          // carried key (as stored)
-    uint32_t px = 0u;
-    uint32_t src = 0u;         // where the carried key was picked up
-    uint32_t t = wave_id;      // this wave's next tile of start positions
-    uint32_t cur = 0u, tb = 0u, tlen = 0u;  // next start inside the current one
+    bool carry[NS];
+    V x[NS];                 // carried key (as stored)
+    uint32_t px[NS], src[NS];
+    int32_t dist[NS];        // carried key's distance to its place
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        carry[q] = false;
+        x[q] = KT::zero();
+        px[q] = src[q] = 0u;
+        dist[q] = 0;
+    }
+    uint32_t t = wave_id;    // this wave's next tile of start positions
+    uint32_t cur = 0u, tb = 0u, tlen = 0u;
     bool tiles_left = true;
     for (;;) {
         // the next tile with start positions left
@@ -325,43 +349,82 @@ __global__ __launch_bounds__(THREADS) void k_cycle(Work w, int L, IpMaps m) {
             cur = 0u;
             t += nwaves;
         }
-        const bool idle = !carry;
-        const uint64_t idle_m = __ballot(idle);
-        if (!tiles_left && idle_m == ~0ull) break;  // no start left, nothing carried
-        uint32_t tgt = IP_NONE;
-        if (idle) {
-            const uint32_t r = cur + lanes_below(idle_m);
-            if (tiles_left && r < tlen) tgt = tb + r;
-        } else {
-            tgt = ip_dest<KB>(w, m, src, w.kind ? KT::enc(x, w.kind) : x);
-            if (tgt == IP_NONE || tgt >= w.n_total) {
-                atomicOr(&ctl->error, ERR_INTERNAL);
-                carry = false;
-                tgt = IP_NONE;
+        bool any = false;
+#pragma unroll
+        for (int q = 0; q < NS; ++q) any = any || carry[q];
+        if (!tiles_left && __ballot(any) == 0ull) break;  // no start left, nothing carried
+        // targets: idle walks take consecutive start positions
+        uint32_t tgt[NS];
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            tgt[q] = IP_NONE;
+            const bool idle = !carry[q];
+            const uint64_t idle_m = __ballot(idle);
+            if (idle) {
+                const uint32_t r = cur + lanes_below(idle_m);
+                if (tiles_left && r < tlen) tgt[q] = tb + r;
+            } else {
+                tgt[q] = (uint32_t)((int32_t)src[q] + dist[q]);
+                if (tgt[q] >= w.n_total) {
+                    atomicOr(&ctl->error, ERR_INTERNAL);
+                    carry[q] = false;
+                    tgt[q] = IP_NONE;
+                }
+            }
+            if (tiles_left) cur += (uint32_t)__builtin_popcountll(idle_m);
+        }
+        // read every target, its segment map entry and, for a start, whether
+        // a walk has claimed it already
+        V y[NS];
+        uint32_t py[NS], claimed[NS];
+        uint4 gm[NS];
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            y[q] = KT::zero();
+            py[q] = claimed[q] = 0u;
+            gm[q] = make_uint4(IP_NONE, 0u, IP_NONE, 0u);
+            if (tgt[q] != IP_NONE) {
+                y[q] = KT::load(w.keys[0], tgt[q]);
+                if (PAY) py[q] = w.pay[0][tgt[q]];
+                gm[q] = m.segmap[tgt[q] / IP_GRANULE];
+                if (!carry[q])
+                    claimed[q] = __hip_atomic_load(ip_word(m.state, tgt[q]), __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
             }
         }
-        if (tiles_left) cur += (uint32_t)__builtin_popcountll(idle_m);
-        // read the target (and, for a start, whether a walk has claimed it)
-        V y = KT::zero();
-        uint32_t py = 0u, claimed = 0u;
-        if (tgt != IP_NONE) {
-            y = KT::load(w.keys[0], tgt);
-            if (PAY) py = w.pay[0][tgt];
-            if (idle) claimed = __hip_atomic_load(ip_word(m.state, tgt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
         ip_wait_all();
-        const bool want = tgt != IP_NONE && !(claimed & ip_bit(tgt));
-        const bool won = ip_claim(m.state, tgt, want);
-        ip_wait_all();
-        if (carry) {
-            KT::store(w.keys[0], tgt, x);
-            if (PAY) w.pay[0][tgt] = px;
+        IpClaim c[NS];
+        bool want[NS];
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            want[q] = tgt[q] != IP_NONE && !(claimed[q] & ip_bit(tgt[q]));
+            c[q] = ip_claim_issue(m.state, tgt[q], want[q]);
         }
-        carry = won;
-        if (won) {
-            x = y;
-            px = py;
-            src = tgt;
+        bool won[NS];
+#pragma unroll
+        for (int q = 0; q < NS; ++q) won[q] = ip_claim_won(c[q], tgt[q], want[q]);
+        ip_wait_all();
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            if (carry[q]) {
+                KT::store(w.keys[0], tgt[q], x[q]);
+                if (PAY) w.pay[0][tgt[q]] = px[q];
+            }
+            carry[q] = won[q];
+            if (won[q]) {
+                x[q] = y[q];
+                px[q] = py[q];
+                src[q] = tgt[q];
+                const IpLoc loc = ip_loc(gm[q], tgt[q]);
+                if (loc.t == IP_NONE) {
+                    atomicOr(&ctl->error, ERR_INTERNAL);
+                    carry[q] = false;
+                } else {
+                    const int wbits = min(IP_K, (int)w.nbits - (int)loc.bitpos);
+                    const uint32_t d = KT::digit(w.kind ? KT::enc(y[q], w.kind) : y[q], (int)loc.bitpos, wbits);
+                    dist[q] = m.dist[(size_t)loc.t * R + d];
+                }
+            }
         }
     }
 }
