@@ -1169,20 +1169,33 @@ __device__ __forceinline__ void aligned_body(const void *base, size_t g0, size_t
     b1 = b0 + (g1 - b0) / VN * VN;
 }
 
+// Loading a sub-array into LDS in two halves, so that a block can issue the
+// next sub-array's loads before it sorts the current one: issue = the 16-byte
+// vector loads of the aligned body into registers; commit = the few keys
+// before and after the body, and everything into LDS (AND/OR on the way).
 template <int KB, int NV, int BT>
-__device__ __forceinline__ void fin_load_keys(const void *src, size_t g0, size_t g1, typename KeyT<KB>::V *lds,
-                                              typename KeyT<KB>::V &a, typename KeyT<KB>::V &o, uint32_t kind) {
-    using KT = KeyT<KB>;
-    using V = typename KT::V;
+__device__ __forceinline__ void fin_issue_keys(const void *src, size_t g0, size_t g1,
+                                               typename KeyT<KB>::V (&v)[NV][Vec<KB>::N]) {
     constexpr int VN = Vec<KB>::N;
     size_t b0, b1;
     aligned_body<VN, KB>(src, g0, g1, b0, b1);
-    V v[NV][VN];
 #pragma unroll
     for (int u = 0; u < NV; ++u) {
         const size_t x = b0 + ((size_t)u * BT + threadIdx.x) * VN;
         if (x < b1) load_vec<KB>(src, x, v[u]);
     }
+}
+
+template <int KB, int NV, int BT>
+__device__ __forceinline__ void fin_commit_keys(const void *src, size_t g0, size_t g1,
+                                                typename KeyT<KB>::V (&v)[NV][Vec<KB>::N],
+                                                typename KeyT<KB>::V *lds, typename KeyT<KB>::V &a,
+                                                typename KeyT<KB>::V &o, uint32_t kind) {
+    using KT = KeyT<KB>;
+    using V = typename KT::V;
+    constexpr int VN = Vec<KB>::N;
+    size_t b0, b1;
+    aligned_body<VN, KB>(src, g0, g1, b0, b1);
     for (size_t i = g0 + threadIdx.x; i < b0; i += BT) {
         const V k = ld_key<KB>(src, i, kind);
         lds[i - g0] = k;
@@ -1210,16 +1223,30 @@ __device__ __forceinline__ void fin_load_keys(const void *src, size_t g0, size_t
     }
 }
 
+template <int KB, int NV, int BT>
+__device__ __forceinline__ void fin_load_keys(const void *src, size_t g0, size_t g1, typename KeyT<KB>::V *lds,
+                                              typename KeyT<KB>::V &a, typename KeyT<KB>::V &o, uint32_t kind) {
+    typename KeyT<KB>::V v[NV][Vec<KB>::N];
+    fin_issue_keys<KB, NV, BT>(src, g0, g1, v);
+    fin_commit_keys<KB, NV, BT>(src, g0, g1, v, lds, a, o, kind);
+}
+
 template <int NV, int BT>
-__device__ __forceinline__ void fin_load_pay(const uint32_t *src, size_t g0, size_t g1, uint32_t *lds) {
+__device__ __forceinline__ void fin_issue_pay(const uint32_t *src, size_t g0, size_t g1, uint4 (&v)[NV]) {
     size_t b0, b1;
     aligned_body<4, 4>(src, g0, g1, b0, b1);
-    uint4 v[NV];
 #pragma unroll
     for (int u = 0; u < NV; ++u) {
         const size_t x = b0 + ((size_t)u * BT + threadIdx.x) * 4;
         if (x < b1) v[u] = *reinterpret_cast<const uint4 *>(src + x);
     }
+}
+
+template <int NV, int BT>
+__device__ __forceinline__ void fin_commit_pay(const uint32_t *src, size_t g0, size_t g1, uint4 (&v)[NV],
+                                               uint32_t *lds) {
+    size_t b0, b1;
+    aligned_body<4, 4>(src, g0, g1, b0, b1);
     for (size_t i = g0 + threadIdx.x; i < b0; i += BT) lds[i - g0] = src[i];
     for (size_t i = b1 + threadIdx.x; i < g1; i += BT) lds[i - g0] = src[i];
 #pragma unroll
@@ -1233,6 +1260,13 @@ __device__ __forceinline__ void fin_load_pay(const uint32_t *src, size_t g0, siz
             d[3] = v[u].w;
         }
     }
+}
+
+template <int NV, int BT>
+__device__ __forceinline__ void fin_load_pay(const uint32_t *src, size_t g0, size_t g1, uint32_t *lds) {
+    uint4 v[NV];
+    fin_issue_pay<NV, BT>(src, g0, g1, v);
+    fin_commit_pay<NV, BT>(src, g0, g1, v, lds);
 }
 
 template <int KB, int BT>
@@ -1529,6 +1563,8 @@ void k_finish(Work w, int cls) {
     __syncthreads();
 
     unsigned long long st_keys = 0ull, st_segs = 0ull;  // flushed once per block
+    constexpr int NVK = (CAP + Vec<KB>::N * BT - 1) / (Vec<KB>::N * BT);
+    constexpr int NVP = (CAP + 4 * BT - 1) / (4 * BT);
     for (uint32_t f = blockIdx.x; f < nfin; f += gridDim.x) {
         const FinEntry fe = uni(w.fin[cls][f]);
         const uint32_t len = fe.info & 0xFFFFu;
@@ -1542,9 +1578,8 @@ void k_finish(Work w, int cls) {
         ++st_segs;
         // load into LDS in input order, AND/OR on the way
         V a = KT::ones(), o = KT::zero();
-        fin_load_keys<KB, (CAP + Vec<KB>::N * BT - 1) / (Vec<KB>::N * BT), BT>(
-            w.keys[parity], fe.begin, (size_t)fe.begin + len, S.keys, a, o, w.kind);
-        if constexpr (PAY) fin_load_pay<(CAP + 4 * BT - 1) / (4 * BT), BT>(w.pay[parity], fe.begin, (size_t)fe.begin + len, S.pay);
+        fin_load_keys<KB, NVK, BT>(w.keys[parity], fe.begin, (size_t)fe.begin + len, S.keys, a, o, w.kind);
+        if constexpr (PAY) fin_load_pay<NVP, BT>(w.pay[parity], fe.begin, (size_t)fe.begin + len, S.pay);
         Canon ca = KT::canon(a), co = KT::canon(o);
 #pragma unroll
         for (int off = 1; off < WAVE; off <<= 1) {
