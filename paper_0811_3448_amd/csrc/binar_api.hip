@@ -722,14 +722,17 @@ int sort_strings(const uint8_t *bytes, uint64_t nbytes, const uint32_t *offs, ui
         hipLaunchKernelGGL(k_str_count, dim3(nblk), dim3(STR_BT), 0, st, reinterpret_cast<const uint4 *>(keys), mark,
                            round, n_active, blk);
         hipLaunchKernelGGL(k_str_scan, dim3(1), dim3(STR_BT), 0, st, blk, nblk, ctl);
-        hipLaunchKernelGGL(k_str_compact, dim3(nblk), dim3(STR_BT), 0, st, reinterpret_cast<const uint4 *>(keys),
-                           mark, round, n_active, blk, ids_c, pos_c, ids_n, pos_n, seg_n, ctl);
         BINAR_HIP_TRY(hipGetLastError());
+        // the totals decide whether a next round exists: the compaction runs
+        // only if it does
         StrCtl h{};
         BINAR_HIP_TRY(hipMemcpyAsync(&h, ctl, sizeof(h), hipMemcpyDeviceToHost, st));
         BINAR_HIP_TRY(hipStreamSynchronize(st));
         if (h.error) return BINAR_EINVAL;
         if (h.n_next == 0) break;
+        hipLaunchKernelGGL(k_str_compact, dim3(nblk), dim3(STR_BT), 0, st, reinterpret_cast<const uint4 *>(keys),
+                           mark, round, n_active, blk, ids_c, pos_c, ids_n, pos_n, seg_n, ctl);
+        BINAR_HIP_TRY(hipGetLastError());
         std::swap(ids_c, ids_n);
         std::swap(pos_c, pos_n);
         std::swap(seg_c, seg_n);

@@ -49,15 +49,46 @@ __global__ __launch_bounds__(256) void k_str_keys(const uint8_t *bytes, uint64_t
         const uint32_t len = e - s;
         const uint32_t rem = len > depth ? len - depth : 0u;
         const uint32_t take = rem < STR_WIN ? rem : STR_WIN;
-        uint8_t k[16];
+        // the window's bytes, little-endian in four words: up to five aligned
+        // 4-byte loads, shifted into place; a word reaching outside the
+        // caller's buffer is read byte by byte, and only the window's bytes
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (take) {
+            const uintptr_t pa = reinterpret_cast<uintptr_t>(bytes) + s + depth;
+            const uintptr_t lo = reinterpret_cast<uintptr_t>(bytes), hi = lo + nbytes;
+            const uintptr_t d0 = pa & ~(uintptr_t)3;
+            const uint32_t off = (uint32_t)(pa - d0);
+            uint32_t wd[5];
 #pragma unroll
-        for (uint32_t j = 0; j < STR_WIN; ++j) k[j] = (j < take) ? bytes[(size_t)s + depth + j] : (uint8_t)0;
-        k[15] = (uint8_t)(rem < 16u ? rem : 16u);
-        uint4 v;
-        v.x = (uint32_t)k[0] | ((uint32_t)k[1] << 8) | ((uint32_t)k[2] << 16) | ((uint32_t)k[3] << 24);
-        v.y = (uint32_t)k[4] | ((uint32_t)k[5] << 8) | ((uint32_t)k[6] << 16) | ((uint32_t)k[7] << 24);
-        v.z = (uint32_t)k[8] | ((uint32_t)k[9] << 8) | ((uint32_t)k[10] << 16) | ((uint32_t)k[11] << 24);
-        v.w = (uint32_t)k[12] | ((uint32_t)k[13] << 8) | ((uint32_t)k[14] << 16) | ((uint32_t)k[15] << 24);
+            for (int q = 0; q < 5; ++q) {
+                const uintptr_t da = d0 + 4u * q;
+                wd[q] = 0u;
+                if (da < pa + take) {
+                    if (da >= lo && da + 4u <= hi) {
+                        wd[q] = *reinterpret_cast<const uint32_t *>(da);
+                    } else {
+#pragma unroll
+                        for (uint32_t b = 0; b < 4; ++b)
+                            if (da + b >= pa && da + b < pa + take)
+                                wd[q] |= (uint32_t)*reinterpret_cast<const uint8_t *>(da + b) << (8u * b);
+                    }
+                }
+            }
+            v.x = __builtin_amdgcn_alignbyte(wd[1], wd[0], off);
+            v.y = __builtin_amdgcn_alignbyte(wd[2], wd[1], off);
+            v.z = __builtin_amdgcn_alignbyte(wd[3], wd[2], off);
+            v.w = __builtin_amdgcn_alignbyte(wd[4], wd[3], off);
+            // bytes past the string's end (or past the window) are zero
+            auto keep = [&](uint32_t word) -> uint32_t {
+                const int n = (int)take - 4 * (int)word;
+                return n >= 4 ? 0xFFFFFFFFu : (n <= 0 ? 0u : ((1u << (8 * n)) - 1u));
+            };
+            v.x &= keep(0);
+            v.y &= keep(1);
+            v.z &= keep(2);
+            v.w &= keep(3);
+        }
+        v.w = (v.w & 0x00FFFFFFu) | ((rem < 16u ? rem : 16u) << 24);
         reinterpret_cast<uint4 *>(keys)[c] = v;
     }
 }

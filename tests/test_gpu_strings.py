@@ -77,3 +77,24 @@ def test_bad_offsets_rejected():
     od = torch.tensor([0, 10, 50, 200], dtype=torch.int32, device="cuda")   # past the buffer
     with pytest.raises(binar.BinarError):
         binar.sort_strings(dd, od, pd)
+
+
+@pytest.mark.parametrize("shift", [1, 2, 3])
+def test_unaligned_byte_buffer(shift):
+    """The byte buffer starts 1..3 bytes past a 4-byte boundary and ends
+    inside a word: the key build reads whole words only inside the buffer."""
+    import torch
+    import paper_0811_3448_amd as binar
+    data, offs = workloads.var_strings(20_000, 300 + shift, 9.0, 5, 0)
+    n = offs.shape[0] - 1
+    backing = torch.zeros(data.shape[0] + shift, dtype=torch.uint8, device="cuda")
+    backing[shift:] = torch.from_numpy(data).cuda()
+    dd = backing[shift:]
+    assert dd.data_ptr() % 4 == shift
+    od = torch.from_numpy(offs.view(np.int32)).cuda()
+    pay = np.arange(n, dtype=np.uint32)
+    pd = torch.from_numpy(pay.view(np.int32)).cuda()
+    print("strings unaligned shift=%d n=%d" % (shift, n), flush=True)
+    binar.sort_strings(dd, od, pd)
+    torch.cuda.synchronize()
+    assert np.array_equal(pd.cpu().numpy().view(np.uint32), strings.sort(data, offs, pay))
