@@ -25,6 +25,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Gkeys/s and % HBM peak, 2^28 uint32+u32 payload; p50/p99 batched-serve latency"
 HBM_PEAK_GBS = 8000.0
+INPLACE_DEFAULT_DIGIT_BITS = 4  # the in-place variant's digit width when none is given
 PROFILES = os.path.join(ROOT, "profiles")
 CSRC = os.path.join(ROOT, "paper_0811_3448_amd", "csrc")
 
@@ -553,7 +554,7 @@ def main() -> int:
     params, source = choose_params(binar, args, kb, has_pay, n, batched=False)
     if args.inplace:
         # fixed pass shape (8-bit digits, 4096-key tiles, chunk prefixes)
-        params, source = binar.Params(finish_max=args.finish_max), "in-place pass shape"
+        params, source = binar.Params(digit_bits=args.digit_bits, finish_max=args.finish_max), "in-place pass shape"
     if name.startswith("f32"):
         # IEEE-754 keys: same kernels, keys read through the order-preserving view
         params = binar.Params(**{**vars(params), "key_kind": binar.KEY_FLOAT})
@@ -690,7 +691,8 @@ def main() -> int:
         "wall_s": round(wall, 4),
     }
     if args.inplace:
-        result["config"].update(digit_bits=8, tile_keys=4096, offsets="chunk prefixes",
+        result["config"].update(digit_bits=args.digit_bits or INPLACE_DEFAULT_DIGIT_BITS, tile_keys=4096,
+                                offsets="chunk prefixes",
                                 finish_max=max(result["config"]["finish_max"], 256))
     del bufs
     torch.cuda.empty_cache()

@@ -252,7 +252,9 @@ size_t binar_strings_workspace_bytes(uint64_t n);
  * and per-tile tables, 1 bit per key and a segment map (see
  * binar_inplace_workspace_bytes: about a sixth of the data for 4-byte keys
  * with payload, against twice the data for binar_sort_ex).
- * params: digit_bits must be 0 or 8, tile_keys 0 or 4096, offsets 0 or 1
+ * params: digit_bits must be 0, 4 or 8 (default 4: twice the passes of 8,
+ * but runs of one digit 16 times longer move together, which is faster),
+ * tile_keys 0 or 4096, offsets 0 or 1
  * (else BINAR_EINVAL); finish_max is raised to at least 256; key_bits and
  * key_kind as for binar_sort_ex.  Asynchronous on stream; binar_stats_read
  * reads its counters.  workspace may be NULL (pool). */

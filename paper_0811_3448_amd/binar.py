@@ -269,7 +269,7 @@ def sort_segmented(keys, seg_offsets, payload=None, stream=None, workspace: Work
 def sort_inplace(keys, payload=None, stream=None, workspace: Workspace | None = None,
                  params: Params | None = None, key_kind: int | None = None):
     """Stable sort like sort(), with no scratch copy of the keys: the passes
-    permute inside keys and payload themselves.  params: digit_bits 0/8,
+    permute inside keys and payload themselves.  params: digit_bits 0/4/8,
     tile_keys 0/4096, offsets 0/1.  Returns keys."""
     _check_tensors(keys, payload)
     params = key_kind_of(keys, params, key_kind)

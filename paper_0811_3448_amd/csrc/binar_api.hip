@@ -521,18 +521,22 @@ int run(void *keys, uint32_t kb, uint64_t n, uint32_t *payload, const uint32_t *
 }
 
 // ------------------------------------------------------------ in place
-// Parameters of the in-place passes: 8-bit digits, 4096-key tiles, chunked
-// piece prefixes, and T at least a segment-map granule.
+// Parameters of the in-place passes: 4- or 8-bit digits (default IP_K_DEFAULT),
+// 4096-key tiles, chunked piece prefixes, and T at least a segment-map
+// granule.
+constexpr uint32_t IP_K_DEFAULT = 4;
+
 int resolve_inplace(uint32_t kb, bool pay, const binar_params *p, Resolved *r) {
-    if (p && ((p->digit_bits && p->digit_bits != (uint32_t)IP_K) || (p->tile_keys && p->tile_keys != IP_TILE) ||
-              p->offsets == 2))
+    if (p && ((p->digit_bits && p->digit_bits != 4u && p->digit_bits != 8u) ||
+              (p->tile_keys && p->tile_keys != IP_TILE) || p->offsets == 2))
         return BINAR_EINVAL;
+    const uint32_t k = (p && p->digit_bits) ? p->digit_bits : IP_K_DEFAULT;
     binar_params d;
     {
         std::lock_guard<std::mutex> lk(g_mu);
         d = g_defaults[kb_index(kb)][pay ? 1 : 0];
     }
-    d.digit_bits = IP_K;
+    d.digit_bits = k;
     d.tile_keys = IP_TILE;
     d.offsets = 1;
     binar_params q = p ? *p : binar_params{};
@@ -545,10 +549,10 @@ int resolve_inplace(uint32_t kb, bool pay, const binar_params *p, Resolved *r) {
     return BINAR_OK;
 }
 
-template <int KB, bool PAY>
+template <int KB, bool PAY, int K>
 int enqueue_inplace(Work w, const Layout &L, char *ws, uint32_t n, hipStream_t st) {
-    constexpr int R = 1 << IP_K;
-    const int passes = ((int)w.nbits + IP_K - 1) / IP_K;
+    constexpr int R = 1 << K;
+    const int passes = ((int)w.nbits + K - 1) / K;
     IpMaps m;
     m.dist = reinterpret_cast<int32_t *>(w.pcnt);  // each row replaces the piece prefix it came from
     m.segmap = reinterpret_cast<uint4 *>(ws + L.segmap);
@@ -562,26 +566,27 @@ int enqueue_inplace(Work w, const Layout &L, char *ws, uint32_t n, hipStream_t s
         hipLaunchKernelGGL(k_init<R>, dim3(1), dim3(THREADS), 0, st, w, nullptr, 1u, n, n);
     }
     // the local sort and the digit count share one grid: it fixes the pieces
-    const uint32_t lg = grid_for(k_local<KB, PAY>, L.max_tiles, IP_BT);
+    const uint32_t lg = grid_for(k_local<KB, PAY, K>, L.max_tiles, IP_BT);
     w.chunk_grid = lg;
     const uint32_t pg = std::max(1u, std::min(L.max_big, 1024u));
-    const uint32_t qg = std::max(1u, std::min(L.max_big * (uint32_t)(R / 32), 2048u));
-    const uint32_t cg = grid_for(k_cycle<KB, PAY, 2>, L.max_tiles);
+    constexpr uint32_t NG = (R < 32) ? 1u : (uint32_t)R / 32u;
+    const uint32_t qg = std::max(1u, std::min(L.max_big * NG, 2048u));
+    const uint32_t cg = grid_for(k_cycle<KB, PAY, 2, K>, L.max_tiles);
     const uint32_t clr = grid_for(k_ip_clear, (L.nstate + THREADS - 1) / THREADS);
-    const uint32_t spg = grid_for(k_small_pairs<KB, PAY>, (L.max_big * (uint32_t)R + THREADS - 1) / THREADS);
+    const uint32_t spg = grid_for(k_small_pairs<KB, PAY, K>, (L.max_big * (uint32_t)R + THREADS - 1) / THREADS);
     for (int j = 0; j < passes; ++j) {
         const int Lc = j & 1;
         {
             Timed tm(st, "k_hist", j);
-            hipLaunchKernelGGL((k_hist<KB, IP_K, false, HIST_BT>), dim3(lg), dim3(HIST_BT), 0, st, w, Lc);
+            hipLaunchKernelGGL((k_hist<KB, K, false, HIST_BT>), dim3(lg), dim3(HIST_BT), 0, st, w, Lc);
         }
         {
             Timed tm(st, "k_pscan", j);
-            hipLaunchKernelGGL((k_pscan<IP_K>), dim3(qg), dim3(THREADS), 0, st, w, Lc);
+            hipLaunchKernelGGL((k_pscan<K>), dim3(qg), dim3(THREADS), 0, st, w, Lc);
         }
         {
             Timed tm(st, "k_plan", j);
-            hipLaunchKernelGGL((k_plan<KB, IP_K>), dim3(pg), dim3(THREADS), 0, st, w, Lc, j);
+            hipLaunchKernelGGL((k_plan<KB, K>), dim3(pg), dim3(THREADS), 0, st, w, Lc, j);
         }
         {
             Timed tm(st, "k_ip_clear", j);
@@ -589,15 +594,15 @@ int enqueue_inplace(Work w, const Layout &L, char *ws, uint32_t n, hipStream_t s
         }
         {
             Timed tm(st, "k_local", j);
-            hipLaunchKernelGGL((k_local<KB, PAY>), dim3(lg), dim3(IP_BT), 0, st, w, Lc, m);
+            hipLaunchKernelGGL((k_local<KB, PAY, K>), dim3(lg), dim3(IP_BT), 0, st, w, Lc, m);
         }
         {
             Timed tm(st, "k_cycle", j);
-            hipLaunchKernelGGL((k_cycle<KB, PAY, 2>), dim3(cg), dim3(THREADS), 0, st, w, Lc, m);
+            hipLaunchKernelGGL((k_cycle<KB, PAY, 2, K>), dim3(cg), dim3(THREADS), 0, st, w, Lc, m);
         }
         {
             Timed tm(st, "k_small_pairs", j);
-            hipLaunchKernelGGL((k_small_pairs<KB, PAY>), dim3(spg), dim3(THREADS), 0, st, w, Lc);
+            hipLaunchKernelGGL((k_small_pairs<KB, PAY, K>), dim3(spg), dim3(THREADS), 0, st, w, Lc);
         }
     }
     {
@@ -635,17 +640,23 @@ int run_inplace(void *keys, uint32_t kb, uint64_t n, uint32_t *payload, const bi
     (void)hipGetLastError();
     char *b = static_cast<char *>(ws);
     const Work w = make_work(L, r, b, keys, payload, (uint32_t)n);
-    switch (kb) {
-        case 4:
-            return payload ? enqueue_inplace<4, true>(w, L, b, (uint32_t)n, st)
-                           : enqueue_inplace<4, false>(w, L, b, (uint32_t)n, st);
-        case 8:
-            return payload ? enqueue_inplace<8, true>(w, L, b, (uint32_t)n, st)
-                           : enqueue_inplace<8, false>(w, L, b, (uint32_t)n, st);
-        default:
-            return payload ? enqueue_inplace<16, true>(w, L, b, (uint32_t)n, st)
-                           : enqueue_inplace<16, false>(w, L, b, (uint32_t)n, st);
+#define BINAR_IP(KK)                                                                                   \
+    switch (kb) {                                                                                      \
+        case 4:                                                                                        \
+            return payload ? enqueue_inplace<4, true, KK>(w, L, b, (uint32_t)n, st)                  \
+                           : enqueue_inplace<4, false, KK>(w, L, b, (uint32_t)n, st);                \
+        case 8:                                                                                        \
+            return payload ? enqueue_inplace<8, true, KK>(w, L, b, (uint32_t)n, st)                  \
+                           : enqueue_inplace<8, false, KK>(w, L, b, (uint32_t)n, st);                \
+        default:                                                                                       \
+            return payload ? enqueue_inplace<16, true, KK>(w, L, b, (uint32_t)n, st)                 \
+                           : enqueue_inplace<16, false, KK>(w, L, b, (uint32_t)n, st);               \
     }
+    if (r.k == 4) {
+        BINAR_IP(4)
+    }
+    BINAR_IP(8)
+#undef BINAR_IP
 }
 
 // ------------------------------------------------------------ strings

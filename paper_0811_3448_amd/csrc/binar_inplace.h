@@ -35,7 +35,7 @@ namespace binar {
 
 constexpr uint32_t IP_GRANULE = 256;     // positions per entry of the segment map
 constexpr uint32_t IP_NONE = 0xFFFFFFFFu;
-constexpr int IP_K = 8;                  // digit bits of the in-place passes
+// digit bits of the in-place passes: 4 or 8 (K below)
 constexpr int IP_BT = 512, IP_ITEMS = 8;  // one tile = 4096 keys
 constexpr uint32_t IP_TILE = IP_BT * IP_ITEMS;
 
@@ -59,10 +59,10 @@ __global__ __launch_bounds__(THREADS) void k_ip_clear(IpMaps m, uint32_t nstate,
         m.segmap[i] = make_uint4(IP_NONE, 0u, IP_NONE, 0u);
 }
 
-template <int KB, bool PAY>
+template <int KB, bool PAY, int K>
 struct LocalLds {
     using V = typename KeyT<KB>::V;
-    static constexpr int R = 1 << IP_K;
+    static constexpr int R = 1 << K;
     static constexpr int NW = IP_BT / WAVE;
     V keys[IP_TILE];
     uint32_t pay[PAY ? IP_TILE : 1];
@@ -74,13 +74,13 @@ struct LocalLds {
 
 // The tiles of list L are cut into gridDim.x chunks exactly as in k_hist, so
 // the piece prefixes line up; the grid must be the one k_hist ran with.
-template <int KB, bool PAY>
+template <int KB, bool PAY, int K>
 __global__ __launch_bounds__(IP_BT) void k_local(Work w, int L, IpMaps m) {
     using KT = KeyT<KB>;
     using V = typename KT::V;
-    constexpr int R = 1 << IP_K;
+    constexpr int R = 1 << K;
     constexpr int NW = IP_BT / WAVE;
-    __shared__ LocalLds<KB, PAY> S;
+    __shared__ LocalLds<KB, PAY, K> S;
     Ctl *ctl = w.ctl;
     if (ctl->error | ctl->overflow) return;
     const unsigned long long lc = ctl->list_ctr[L];
@@ -120,7 +120,7 @@ __global__ __launch_bounds__(IP_BT) void k_local(Work w, int L, IpMaps m) {
             __syncthreads();
         }
         const uint32_t bitpos = seg.info & 0xFFu;
-        const int wbits = min(IP_K, (int)w.nbits - (int)bitpos);
+        const int wbits = min(K, (int)w.nbits - (int)bitpos);
         const uint32_t off = (t - seg.tile_start) * IP_TILE;
         const uint32_t tlen = min(IP_TILE, seg.len - off);
         const uint32_t tb = seg.begin + off;
@@ -303,11 +303,11 @@ __device__ __forceinline__ IpLoc ip_loc(uint4 gm, uint32_t i) {
 // flight together), and the distance of a picked-up key is loaded right
 // after its claim, so a step waits for three memory round trips: distance,
 // read, claim.
-template <int KB, bool PAY, int NS>
+template <int KB, bool PAY, int NS, int K>
 __global__ __launch_bounds__(THREADS) void k_cycle(Work w, int L, IpMaps m) {
     using KT = KeyT<KB>;
     using V = typename KT::V;
-    constexpr uint32_t R = 1u << IP_K;
+    constexpr uint32_t R = 1u << K;
     Ctl *ctl = w.ctl;
     if (ctl->error | ctl->overflow) return;
     const unsigned long long lc = ctl->list_ctr[L];
@@ -420,7 +420,7 @@ __global__ __launch_bounds__(THREADS) void k_cycle(Work w, int L, IpMaps m) {
                     atomicOr(&ctl->error, ERR_INTERNAL);
                     carry[q] = false;
                 } else {
-                    const int wbits = min(IP_K, (int)w.nbits - (int)loc.bitpos);
+                    const int wbits = min(K, (int)w.nbits - (int)loc.bitpos);
                     const uint32_t d = KT::digit(w.kind ? KT::enc(y[q], w.kind) : y[q], (int)loc.bitpos, wbits);
                     dist[q] = m.dist[(size_t)loc.t * R + d];
                 }
@@ -432,39 +432,39 @@ __global__ __launch_bounds__(THREADS) void k_cycle(Work w, int L, IpMaps m) {
 // Children of 2..SMALL_MAX keys of the segments partitioned with list L,
 // taken from its count and base tables: each wave takes 64 (segment, digit)
 // pairs at a time and ranks the small ones, packed into its lanes, in place.
-template <int KB, bool PAY>
+template <int KB, bool PAY, int K>
 __global__ __launch_bounds__(THREADS) void k_small_pairs(Work w, int L) {
     using KT = KeyT<KB>;
     using V = typename KT::V;
-    constexpr int R = 1 << IP_K;
+    constexpr uint32_t R = 1u << K;
     Ctl *ctl = w.ctl;
     if (ctl->error | ctl->overflow) return;
     const unsigned long long lc = ctl->list_ctr[L];
     const uint32_t nslots = (uint32_t)(lc >> 32);
     if (nslots == 0) return;
-    const uint32_t npairs = nslots * (uint32_t)R;
+    const uint32_t npairs = nslots * R;
     const int lane = lane_id();
     const uint32_t wave_id = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
     const uint32_t nwaves = gridDim.x * (blockDim.x / WAVE);
     const Canon km = canon_lead_mask((int)w.nbits);
     unsigned long long st_keys = 0ull, st_segs = 0ull;
     for (uint32_t e0 = wave_id * WAVE; e0 < npairs; e0 += nwaves * WAVE) {
-        // 64 pairs never straddle two segments: R is a multiple of 64
-        const uint32_t s = e0 / R;
-        const SegEntry seg = uni(w.list[L][s]);
-        if (((seg.info >> 16) & SEG_SKIP) || ((seg.info >> 8) & 1u)) continue;
         const uint32_t e = e0 + lane;
-        const uint32_t c = w.counts[L][e];
         uint32_t b = 0u, len = 0u;
-        if (c >= 2u && c <= SMALL_MAX) {
-            b = w.bases[L][e];
-            len = c;
-            if (b < seg.begin || b - seg.begin + c > seg.len) {
-                atomicOr(&ctl->error, ERR_INTERNAL);
-                len = 0u;
-            } else {
-                st_keys += len;
-                ++st_segs;
+        if (e < npairs) {
+            const SegEntry seg = w.list[L][e / R];
+            const bool moved = !((seg.info >> 16) & SEG_SKIP) && !((seg.info >> 8) & 1u);
+            const uint32_t c = moved ? w.counts[L][e] : 0u;
+            if (c >= 2u && c <= SMALL_MAX) {
+                b = w.bases[L][e];
+                len = c;
+                if (b < seg.begin || b - seg.begin + c > seg.len) {
+                    atomicOr(&ctl->error, ERR_INTERNAL);
+                    len = 0u;
+                } else {
+                    st_keys += len;
+                    ++st_segs;
+                }
             }
         }
         wave_pack(len, [&](int l, uint32_t i, int head, bool act, uint32_t el, uint32_t ml) {

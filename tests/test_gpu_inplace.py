@@ -113,7 +113,7 @@ def test_rejects_other_shapes():
     import torch
     import paper_0811_3448_amd as binar
     k = torch.zeros(1000, dtype=torch.int32, device="cuda")
-    for bad in (P(digit_bits=4), P(tile_keys=8192), P(offsets=2)):
+    for bad in (P(digit_bits=5), P(digit_bits=1), P(tile_keys=8192), P(offsets=2)):
         with pytest.raises(binar.BinarError):
             binar.sort_inplace(k, params=bad)
 
@@ -124,3 +124,28 @@ def test_workspace_is_small():
     ip = binar.inplace_workspace_bytes(4, n, True)
     pp = binar.workspace_bytes(4, n, True)
     assert ip < 0.25 * 8 * n < pp
+
+
+@pytest.mark.parametrize("k", [4, 8])
+@pytest.mark.parametrize("kb", [4, 8, 16])
+def test_digit_widths(k, kb):
+    """4-bit digits: twice the passes, runs of one digit sixteen times longer."""
+    n = 500_003
+    keys = {4: lambda: workloads.u32_and4(n, 760), 8: lambda: workloads.u64_uniform(n, 761),
+            16: lambda: workloads.str16(n, 762, 5)}[kb]()
+    compare(keys, digit_bits=k)
+    compare(keys, with_payload=False, digit_bits=k, finish_max=300)
+
+
+def test_digit_4_partial_and_kinds():
+    n = 200_003
+    keys = workloads.u64_uniform(n, 770)
+    pay = np.arange(n, dtype=np.uint32)
+    gk, gp, _ = ip_sort(keys, pay, params=P(key_bits=22, digit_bits=4))
+    rk, rp = oracle.partition(keys, pay, 22)
+    assert np.array_equal(gp, rp) and np.array_equal(gk, rk)
+    rng = np.random.default_rng(771)
+    ik = rng.integers(-1000, 1000, n, dtype=np.int64).astype(np.int32).view(np.uint32)
+    gk, gp, _ = ip_sort(ik, pay, params=P(key_kind=orders.SIGNED, digit_bits=4))
+    rk, rp = orders.sort(ik, pay, orders.SIGNED)
+    assert np.array_equal(gp, rp) and np.array_equal(gk, rk)
