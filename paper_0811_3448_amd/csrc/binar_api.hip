@@ -525,6 +525,7 @@ int run(void *keys, uint32_t kb, uint64_t n, uint32_t *payload, const uint32_t *
 // 4096-key tiles, chunked piece prefixes, and T at least a segment-map
 // granule.
 constexpr uint32_t IP_K_DEFAULT = 4;
+constexpr int IP_WALKS = 4;  // walks per lane in the cycle walk
 
 int resolve_inplace(uint32_t kb, bool pay, const binar_params *p, Resolved *r) {
     if (p && ((p->digit_bits && p->digit_bits != 4u && p->digit_bits != 8u) ||
@@ -571,7 +572,7 @@ int enqueue_inplace(Work w, const Layout &L, char *ws, uint32_t n, hipStream_t s
     const uint32_t pg = std::max(1u, std::min(L.max_big, 1024u));
     constexpr uint32_t NG = (R < 32) ? 1u : (uint32_t)R / 32u;
     const uint32_t qg = std::max(1u, std::min(L.max_big * NG, 2048u));
-    const uint32_t cg = grid_for(k_cycle<KB, PAY, 2, K>, L.max_tiles);
+    const uint32_t cg = grid_for(k_cycle<KB, PAY, IP_WALKS, K>, L.max_tiles);
     const uint32_t clr = grid_for(k_ip_clear, (L.nstate + THREADS - 1) / THREADS);
     const uint32_t spg = grid_for(k_small_pairs<KB, PAY, K>, (L.max_big * (uint32_t)R + THREADS - 1) / THREADS);
     for (int j = 0; j < passes; ++j) {
@@ -598,7 +599,7 @@ int enqueue_inplace(Work w, const Layout &L, char *ws, uint32_t n, hipStream_t s
         }
         {
             Timed tm(st, "k_cycle", j);
-            hipLaunchKernelGGL((k_cycle<KB, PAY, 2, K>), dim3(cg), dim3(THREADS), 0, st, w, Lc, m);
+            hipLaunchKernelGGL((k_cycle<KB, PAY, IP_WALKS, K>), dim3(cg), dim3(THREADS), 0, st, w, Lc, m);
         }
         {
             Timed tm(st, "k_small_pairs", j);
