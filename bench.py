@@ -508,6 +508,8 @@ def main() -> int:
     ap.add_argument("--str-log2", type=int, default=24, help="str_var workload: log2 of the string count")
     ap.add_argument("--lin-dump", default="", help="linearity workload: write n,ms,passes CSV here")
     ap.add_argument("--serve-budget-gib", type=int, default=32)
+    ap.add_argument("--no-copy-ceiling", action="store_true",
+                    help="skip the 2 GiB copy (counter runs calibrate on the bench's 1 GiB copies alone)")
     ap.add_argument("--inplace", action="store_true",
                     help="single-array workloads: the in-place variant (no scratch copy of the keys)")
     args = ap.parse_args()
@@ -696,10 +698,11 @@ def main() -> int:
                                 finish_max=max(result["config"]["finish_max"], 256))
     del bufs
     torch.cuda.empty_cache()
-    cc = copy_ceiling(torch, dev)
-    result["copy_ceiling"] = cc
-    result["roofline"]["frac_of_copy"] = round(achieved / cc["gbs"], 4)
-    result["sort_roofline"]["frac_of_copy"] = round(total_bytes / (ms_per_step * 1e-3) / 1e9 / cc["gbs"], 4)
+    if not args.no_copy_ceiling:
+        cc = copy_ceiling(torch, dev)
+        result["copy_ceiling"] = cc
+        result["roofline"]["frac_of_copy"] = round(achieved / cc["gbs"], 4)
+        result["sort_roofline"]["frac_of_copy"] = round(total_bytes / (ms_per_step * 1e-3) / 1e9 / cc["gbs"], 4)
     if not args.no_cpu_baseline:
         print("bench: CPU oracle sample", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(keys_np, args.cpu_sample_log2)
