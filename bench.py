@@ -561,7 +561,9 @@ def main() -> int:
         # IEEE-754 keys: same kernels, keys read through the order-preserving view
         params = binar.Params(**{**vars(params), "key_kind": binar.KEY_FLOAT})
     pp_ws_bytes = binar.workspace_bytes(kb, n, has_pay, 1, params)
-    ip_ws_bytes = binar.inplace_workspace_bytes(kb, n, has_pay, params)
+    # the in-place variant has its own pass shape: size it with that
+    ip_params = params if args.inplace else binar.Params(key_kind=params.key_kind)
+    ip_ws_bytes = binar.inplace_workspace_bytes(kb, n, has_pay, ip_params)
     ws = binar.Workspace(ip_ws_bytes if args.inplace else pp_ws_bytes, device=dev)
     sort_fn = binar.sort_inplace if args.inplace else binar.sort
     stream = torch.cuda.current_stream()

@@ -250,8 +250,8 @@ size_t binar_strings_workspace_bytes(uint64_t n);
  * over itself, and then moves every key to its place by following the
  * cycles of the pass's permutation.  The workspace holds only per-segment
  * and per-tile tables, 1 bit per key and a segment map (see
- * binar_inplace_workspace_bytes: about a sixth of the data for 4-byte keys
- * with payload, against twice the data for binar_sort_ex).
+ * binar_inplace_workspace_bytes: about 5% of the data for 4-byte keys with
+ * payload and 4-bit digits, against twice the data for binar_sort_ex).
  * params: digit_bits must be 0, 4 or 8 (default 4: twice the passes of 8,
  * but runs of one digit 16 times longer move together, which is faster),
  * tile_keys 0 or 4096, offsets 0 or 1
