@@ -76,3 +76,80 @@ def test_full_size(name):
     ph = pout[torch.tensor(ranks, device="cuda")].cpu().numpy()
     for j, r, k, p in zip(js, ranks, kh, ph):
         assert k == keys[j] and p == j, "input %d should sit at output %d" % (j, r)
+
+
+@pytest.mark.parametrize("name", ["u32_2e28_uniform", "u64_2e27_uniform", "u64_2e27_zipf"])
+def test_full_size_inplace(name):
+    """The in-place variant at full size, in the configuration
+    `bench.py --inplace` times (library defaults: 4-bit digits)."""
+    import torch
+    import paper_0811_3448_amd as binar
+    kb, n, has_pay, desc = workloads.SINGLE[name]
+    print("full size in place %s: %s" % (name, desc), flush=True)
+    keys = workloads.single_keys(name)
+    dt = np.int32 if kb == 4 else np.int64
+    kin = torch.from_numpy(keys.view(dt)).cuda()
+    kout = kin.clone()
+    pout = torch.arange(n, dtype=torch.int32, device="cuda")
+    binar.sort_inplace(kout, pout, params=binar.Params())
+    torch.cuda.synchronize()
+    assert binar.stats()["status"] == 0
+    print("  sorted in place; device checks", flush=True)
+    device_checks(kin, kout, pout, kb)
+    del kin
+    rng = np.random.default_rng(n + kb + 1)
+    js = rng.integers(0, n, SAMPLES).tolist() + [0, n - 1]
+    ranks = [stable_rank_u(keys, j) for j in js]
+    kh = kout[torch.tensor(ranks, device="cuda")].cpu().numpy().view(keys.dtype)
+    ph = pout[torch.tensor(ranks, device="cuda")].cpu().numpy()
+    for j, r, k, p in zip(js, ranks, kh, ph):
+        assert k == keys[j] and p == j, "input %d should sit at output %d" % (j, r)
+
+
+@pytest.mark.parametrize("prefix", [0, 40])
+def test_full_size_strings(prefix):
+    """2^24 variable-length strings as `bench.py --workload str_var` sorts
+    them: every adjacent pair of outputs in order (bytes, then input index
+    on equal strings: together with a permutation check this is the unique
+    stable order), checked on the host."""
+    import torch
+    import paper_0811_3448_amd as binar
+    n = 1 << 24
+    data, offs = workloads.var_strings(n, 0x5771 + prefix, 20.0, 26, prefix)
+    print("full size strings prefix=%d n=%d bytes=%d" % (prefix, n, data.shape[0]), flush=True)
+    dd = torch.from_numpy(data).cuda()
+    od = torch.from_numpy(offs.view(np.int32)).cuda()
+    pd = torch.arange(n, dtype=torch.int32, device="cuda")
+    binar.sort_strings(dd, od, pd)
+    torch.cuda.synchronize()
+    p = pd.cpu().numpy().view(np.uint32).astype(np.int64)
+    seen = np.zeros(n, dtype=bool)
+    seen[p] = True
+    assert seen.all(), "not a permutation"
+    # adjacent pairs: compare the strings byte-wise, vectorised over pairs by
+    # a zero-padded fixed-width copy plus the lengths (the letters are never
+    # zero, so padding never hides a difference)
+    o = offs.astype(np.int64)
+    lens = o[1:] - o[:-1]
+    width = int(lens.max())
+    pad = np.zeros((n, width), dtype=np.uint8)
+    idx = np.arange(width)[None, :]
+    for lo in range(0, n, 1 << 20):
+        hi = min(n, lo + (1 << 20))
+        ln = lens[lo:hi, None]
+        src = np.minimum(o[lo:hi, None] + np.minimum(idx, np.maximum(ln - 1, 0)), data.shape[0] - 1)
+        pad[lo:hi] = np.where(idx < ln, data[src], 0)
+    a, b = p[:-1], p[1:]
+    for lo in range(0, n - 1, 1 << 20):
+        hi = min(n - 1, lo + (1 << 20))
+        pa, pb = pad[a[lo:hi]], pad[b[lo:hi]]
+        ne = pa != pb
+        first = np.where(ne.any(axis=1), ne.argmax(axis=1), width)
+        rows = np.arange(hi - lo)
+        ca = np.where(first < width, pa[rows, np.minimum(first, width - 1)], 0).astype(np.int64)
+        cb = np.where(first < width, pb[rows, np.minimum(first, width - 1)], 0).astype(np.int64)
+        la, lb = lens[a[lo:hi]], lens[b[lo:hi]]
+        # differing byte decides; else the shorter (a prefix) first; else input order
+        less = np.where(first < np.minimum(la, lb), ca < cb,
+                        np.where(la != lb, la < lb, a[lo:hi] < b[lo:hi]))
+        assert less.all(), "pair %d out of order" % (lo + int(np.argmin(less)))
