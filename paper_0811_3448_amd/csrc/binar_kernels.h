@@ -1635,6 +1635,219 @@ void k_finish(Work w, int cls) {
     }
 }
 
+// ----------------------------------------------------------- k_finish_wave
+// Sub-arrays of up to FW_CAP keys (the smallest LDS class), one per wave:
+// the same steps as k_finish -- AND/OR, the two leading varying windows as
+// LSD passes in LDS, tied runs ranked in the wave, passes over every varying
+// bit if a run is longer than 64 -- in a slice of LDS of the wave's own,
+// with wave-level scans instead of block barriers.  A workgroup per short
+// sub-array spends most of its time in barriers; here the waves of a block
+// never wait for each other.
+constexpr int FW_CAP = 1024;
+constexpr int FW_ITEMS = FW_CAP / WAVE;
+
+template <int KB, bool PAY>
+struct WaveFinLds {
+    using V = typename KeyT<KB>::V;
+    V keys[FW_CAP];
+    uint32_t pay[PAY ? FW_CAP : 1];
+    alignas(8) uint32_t tbl[2 * 256];  // lane masks; between passes the list of tied runs
+    uint32_t wh[256];
+    uint32_t long_run;
+};
+
+// Stable passes over the varying bits in [bitpos, end] of the wave's slice,
+// least significant window of up to 8 bits first.
+template <int KB, bool PAY>
+__device__ __forceinline__ void wave_passes(WaveFinLds<KB, PAY> &S, Canon diff, int bitpos, int end, uint32_t len) {
+    using KT = KeyT<KB>;
+    using V = typename KT::V;
+    constexpr int R = 256;
+    const int lane = lane_id();
+    int hib = last_set_below(diff, bitpos, end + 1);
+    while (hib >= bitpos) {
+        const int lo = max(bitpos, hib - 7);
+        const int wbits = hib - lo + 1;
+        V key[FW_ITEMS];
+        uint32_t dg[FW_ITEMS], rnk[FW_ITEMS], pv[FW_ITEMS];
+#pragma unroll
+        for (int j = 0; j < FW_ITEMS; ++j) {
+            const uint32_t e = (uint32_t)lane + j * WAVE;
+            key[j] = (e < len) ? S.keys[e] : KT::zero();
+            dg[j] = KT::digit(key[j], lo, wbits);
+        }
+        wave_rank<R, RANK_GROUP, FW_ITEMS, false>(dg, (uint32_t)lane, len, S.tbl, S.wh, rnk);
+#pragma unroll
+        for (int j = 0; j < FW_ITEMS; ++j) {
+            const uint32_t e = (uint32_t)lane + j * WAVE;
+            pv[j] = (PAY && e < len) ? S.pay[e] : 0u;
+        }
+        // exclusive scan of the digit counts: lane l holds digits 4l .. 4l+3
+        {
+            const uint32_t c0 = S.wh[4 * lane], c1 = S.wh[4 * lane + 1], c2 = S.wh[4 * lane + 2],
+                           c3 = S.wh[4 * lane + 3];
+            const uint32_t sum = c0 + c1 + c2 + c3;
+            uint32_t x = sum;
+#pragma unroll
+            for (int o = 1; o < WAVE; o <<= 1) {
+                const uint32_t y = __shfl_up(x, o, WAVE);
+                if (lane >= o) x += y;
+            }
+            const uint32_t b = x - sum;
+            S.wh[4 * lane] = b;
+            S.wh[4 * lane + 1] = b + c0;
+            S.wh[4 * lane + 2] = b + c0 + c1;
+            S.wh[4 * lane + 3] = b + c0 + c1 + c2;
+        }
+#pragma unroll
+        for (int j = 0; j < FW_ITEMS; ++j) {
+            const uint32_t e = (uint32_t)lane + j * WAVE;
+            if (e < len) {
+                const uint32_t pos = S.wh[dg[j]] + rnk[j];
+                S.keys[pos] = key[j];
+                if (PAY) S.pay[pos] = pv[j];
+            }
+        }
+        for (int i = lane; i < R; i += WAVE) S.wh[i] = 0u;
+        hib = last_set_below(diff, bitpos, lo);
+    }
+}
+
+// Tied runs of the wave's slice after sorting by bits [0, pe]: runs of up to
+// 64 keys ranked in the wave on the leading nb bits (packed, as in
+// fix_runs); true, with nothing of a longer run moved, if a run is longer.
+template <int KB, bool PAY>
+__device__ bool wave_fix_runs(WaveFinLds<KB, PAY> &S, int pe, uint32_t len, int nb) {
+    using KT = KeyT<KB>;
+    using V = typename KT::V;
+    typedef uint16_t __attribute__((may_alias)) pos16_t;
+    static_assert(2 * 256 * 2 >= FW_CAP / 2, "run list must hold every possible run start");
+    pos16_t *list = reinterpret_cast<pos16_t *>(&S.tbl[0]);
+    const int lane = lane_id();
+    Canon pm;
+    pm.hi = pe >= 63 ? ~0ull : ~(~0ull >> (pe + 1));
+    pm.lo = pe >= 127 ? ~0ull : (pe < 64 ? 0ull : ~(~0ull >> (pe - 63)));
+    const Canon km = canon_lead_mask(nb);
+    bool lng = false;
+    // run starts in position order (position = lane + 64 j)
+    uint32_t nruns = 0;
+#pragma unroll
+    for (int j = 0; j < FW_ITEMS; ++j) {
+        const uint32_t p = (uint32_t)lane + j * WAVE;
+        bool st = false;
+        if (p + 1 < len) {
+            const Canon k = KT::canon(S.keys[p]);
+            st = canon_eq_under(KT::canon(S.keys[p + 1]), k, pm) &&
+                 (p == 0 || !canon_eq_under(KT::canon(S.keys[p - 1]), k, pm));
+        }
+        const uint64_t b = __ballot(st);
+        if (st) list[nruns + lanes_below(b)] = (uint16_t)p;
+        nruns += (uint32_t)__popcll(b);
+    }
+    for (uint32_t r0 = 0; r0 < nruns; r0 += WAVE) {
+        uint32_t s0 = 0u, L = 0u;
+        if (r0 + (uint32_t)lane < nruns) {
+            s0 = list[r0 + lane];
+            const Canon ks = KT::canon(S.keys[s0]);
+            L = 2u;
+            while (L <= (uint32_t)WAVE && s0 + L < len && canon_eq_under(KT::canon(S.keys[s0 + L]), ks, pm)) ++L;
+            if (L > (uint32_t)WAVE) {
+                lng = true;
+                L = 0u;
+            }
+        }
+        wave_pack(L, [&](int l, uint32_t i, int head, bool act, uint32_t el, uint32_t ml) {
+            const uint32_t s = __shfl(s0, l, WAVE);
+            V k = KT::zero();
+            uint32_t pv = 0u;
+            if (act) {
+                k = S.keys[s + i];
+                if (PAY) pv = S.pay[s + i];
+            }
+            Canon ck = KT::canon(k);
+            ck.hi &= km.hi;
+            ck.lo &= km.lo;
+            const uint32_t r = pack_rank<KB>(ck, i, el, head, ml);
+            if (act) {
+                S.keys[s + r] = k;
+                if (PAY) S.pay[s + r] = pv;
+            }
+        });
+    }
+    // the ranking tables start at zero
+    for (uint32_t i = lane; i < (nruns + 1u) / 2u; i += WAVE) S.tbl[i] = 0u;
+    return __ballot(lng) != 0ull;
+}
+
+template <int KB>
+struct FinWaves {
+    static constexpr int n = (KB == 16) ? 2 : 4;  // waves per block: LDS per wave grows with the key
+};
+
+template <int KB, bool PAY>
+__global__ __launch_bounds__(FinWaves<KB>::n * WAVE) void k_finish_wave(Work w, int cls) {
+    using KT = KeyT<KB>;
+    using V = typename KT::V;
+    constexpr int NWB = FinWaves<KB>::n;
+    const int NB = (int)w.nbits;
+    __shared__ WaveFinLds<KB, PAY> SS[NWB];
+    Ctl *ctl = w.ctl;
+    if (ctl->error | ctl->overflow) return;
+    const uint32_t nfin = min(ctl->fin_ctr[cls], w.max_fin[cls]);
+    const int wv = threadIdx.x / WAVE, lane = lane_id();
+    WaveFinLds<KB, PAY> &S = SS[wv];
+    for (int i = lane; i < 2 * 256; i += WAVE) S.tbl[i] = 0u;
+    for (int i = lane; i < 256; i += WAVE) S.wh[i] = 0u;
+    const uint32_t gw = blockIdx.x * NWB + wv, nw = gridDim.x * NWB;
+    unsigned long long st_keys = 0ull, st_segs = 0ull;
+    for (uint32_t f = gw; f < nfin; f += nw) {
+        const FinEntry fe = uni(w.fin[cls][f]);
+        const uint32_t len = fe.info & 0xFFFFu;
+        const int bitpos = (int)((fe.info >> 16) & 0xFFu);
+        const uint32_t parity = (fe.info >> 24) & 1u;
+        if (len > (uint32_t)FW_CAP || (size_t)fe.begin + len > w.n_total) {
+            if (lane == 0) atomicOr(&ctl->error, ERR_INTERNAL);
+            continue;
+        }
+        st_keys += len;
+        ++st_segs;
+        V a = KT::ones(), o = KT::zero();
+        for (uint32_t p = lane; p < len; p += WAVE) {
+            const V k = ld_key<KB>(w.keys[parity], (size_t)fe.begin + p, w.kind);
+            S.keys[p] = k;
+            a = KT::vand(a, k);
+            o = KT::vor(o, k);
+            if (PAY) S.pay[p] = w.pay[parity][fe.begin + p];
+        }
+        Canon ca = KT::canon(a), co = KT::canon(o);
+#pragma unroll
+        for (int off = 1; off < WAVE; off <<= 1) {
+            ca.hi &= __shfl_xor(ca.hi, off, WAVE);
+            ca.lo &= __shfl_xor(ca.lo, off, WAVE);
+            co.hi |= __shfl_xor(co.hi, off, WAVE);
+            co.lo |= __shfl_xor(co.lo, off, WAVE);
+        }
+        const Canon diff{ca.hi ^ co.hi, ca.lo ^ co.lo};
+        const int lb = last_set_below(diff, bitpos, NB);
+        if (lb < bitpos && parity == 0u) continue;  // nothing varies and the keys sit in A
+        if (lb >= bitpos) {
+            const int fb = first_set_from(diff, bitpos, NB);
+            const int f2 = first_set_from(diff, min(fb + 8, NB), NB);
+            const int pe = (f2 >= NB) ? lb : min(lb, f2 + 7);
+            wave_passes<KB, PAY>(S, diff, bitpos, pe, len);
+            if (pe < lb && wave_fix_runs<KB, PAY>(S, pe, len, NB)) wave_passes<KB, PAY>(S, diff, bitpos, lb, len);
+        }
+        for (uint32_t p = lane; p < len; p += WAVE) {
+            KT::store(w.keys[0], (size_t)fe.begin + p, raw_key<KB>(S.keys[p], w.kind));
+            if (PAY) w.pay[0][fe.begin + p] = S.pay[p];
+        }
+    }
+    if (lane == 0 && st_segs) {
+        atomicAdd(&ctl->fin_keys[cls], st_keys);
+        atomicAdd(&ctl->fin_segs[cls], st_segs);
+    }
+}
+
 // ---------------------------------------------------------- k_finish_small
 // Sub-arrays of 2 .. SMALL_MAX keys.  A block per sub-array would spend its
 // time on barriers; instead each wave takes 64 list entries at a time and
