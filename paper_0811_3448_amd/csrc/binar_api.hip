@@ -393,17 +393,17 @@ void launch_finish(const Work &w, const Layout &L, hipStream_t st) {
 // 2^24-string sort measured 2.43 ms against 2.29).
 template <int KB, bool PAY>
 void launch_finish_wave(const Work &w, const Layout &L, hipStream_t st) {
-    static_assert(FinShape<KB>::bt[0] * FinShape<KB>::items[0] == FW_CAP, "class 0 is the wave finish");
     if constexpr (KB == 16) {
         launch_finish<KB, PAY, 0>(w, L, st);
-        return;
+    } else {
+        static_assert(FinShape<KB>::bt[0] * FinShape<KB>::items[0] == FW_CAP, "class 0 is the wave finish");
+        if (!L.max_fin[0]) return;
+        constexpr int NWB = FinWaves<KB>::n;
+        Timed tm(st, "k_finish0", -1);
+        const uint32_t blocks = (L.max_fin[0] + NWB - 1) / NWB;
+        hipLaunchKernelGGL((k_finish_wave<KB, PAY>), dim3(grid_for(k_finish_wave<KB, PAY>, blocks, NWB * WAVE)),
+                           dim3(NWB * WAVE), 0, st, w, 0);
     }
-    if (!L.max_fin[0]) return;
-    constexpr int NWB = FinWaves<KB>::n;
-    Timed tm(st, "k_finish0", -1);
-    const uint32_t blocks = (L.max_fin[0] + NWB - 1) / NWB;
-    hipLaunchKernelGGL((k_finish_wave<KB, PAY>), dim3(grid_for(k_finish_wave<KB, PAY>, blocks, NWB * WAVE)),
-                       dim3(NWB * WAVE), 0, st, w, 0);
 }
 
 template <int KB, int K, int TILE, bool PAY, bool LB>
