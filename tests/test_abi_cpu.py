@@ -96,3 +96,35 @@ def test_key_kind_params(lib):
     with pytest.raises(BinarError):
         resolve_params(4, True, Params(key_kind=3))
     assert default_params(4, True).key_kind == 0                    # never part of the defaults
+
+
+def test_inplace_parameters_and_workspace(lib):
+    """The in-place entry point's pass shape is checked before any device
+    work, and its workspace is a small fraction of the data (no second copy
+    of the keys), against the ping-pong sort's."""
+    from paper_0811_3448_amd import binar
+    n = 1 << 28
+    ip = binar.inplace_workspace_bytes(4, n, True)
+    assert 0 < ip < 0.1 * 8 * n < 8 * n < binar.workspace_bytes(4, n, True)
+    assert binar.inplace_workspace_bytes(4, n, True, binar.Params(digit_bits=8)) > ip  # 256-way tables
+    for kb in (4, 8, 16):
+        assert binar.inplace_workspace_bytes(kb, 1000, False) > 0
+    for bad in (binar.Params(digit_bits=5), binar.Params(digit_bits=1), binar.Params(tile_keys=8192),
+                binar.Params(offsets=2)):
+        assert binar.inplace_workspace_bytes(4, 1000, True, bad) == 0
+        p = bad.c()
+        assert lib.binar_sort_inplace(ctypes.c_void_p(0x10000), 4, 1000, None, ctypes.byref(p),
+                                      None, None, 0) == -1
+    assert lib.binar_sort_inplace(ctypes.c_void_p(0x10000), 3, 1000, None, None, None, None, 0) == -1
+    assert lib.binar_sort_inplace(None, 4, 1, None, None, None, None, 0) == 0  # base case
+    assert lib.binar_sort_inplace(ctypes.c_void_p(0x10000), 4, 1 << 30, None, None, None, None, 0) == -2
+
+
+def test_strings_argument_errors(lib):
+    from paper_0811_3448_amd import binar
+    assert binar.strings_workspace_bytes(1000) > 0
+    vp = ctypes.c_void_p
+    assert lib.binar_sort_strings(None, 0, None, 1, None, None, None, 0) == 0      # one string: nothing to do
+    assert lib.binar_sort_strings(vp(0x10000), 10, None, 5, vp(0x20000), None, None, 0) == -1  # NULL offsets
+    assert lib.binar_sort_strings(vp(0x10000), 10, vp(0x20000), 5, None, None, None, 0) == -1  # NULL payload
+    assert lib.binar_sort_strings(vp(0x10000), 10, vp(0x20000), 1 << 30, vp(0x30000), None, None, 0) == -2
