@@ -208,6 +208,26 @@ constexpr int RANK_GROUP = 2;  // steps per group of wave_rank
 template <int R, int G, int ITEMS, bool FULL>
 __device__ __forceinline__ void wave_rank(const uint32_t (&dg)[ITEMS], uint32_t ebase, uint32_t len,
                                           uint32_t *tbl, uint32_t *whist, uint32_t (&rnk)[ITEMS]) {
+    if constexpr (R == 2) {
+        // the paper's one-bit step: a ballot of the bit gives each lane the
+        // lanes below it with the same bit (mbcnt), its popcount the wave's
+        // total; running totals carry the order across steps
+        uint32_t c0 = 0u, c1 = 0u;
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const bool valid = FULL || ebase + (uint32_t)j * WAVE < len;
+            const uint64_t m1 = __ballot(valid && dg[j] != 0u), m0 = __ballot(valid && dg[j] == 0u);
+            rnk[j] = dg[j] ? c1 + lanes_below(m1) : c0 + lanes_below(m0);
+            c0 += (uint32_t)__popcll(m0);
+            c1 += (uint32_t)__popcll(m1);
+        }
+        if (lane_id() == 0) {
+            whist[0] += c0;
+            whist[1] += c1;
+        }
+        (void)tbl;
+        return;
+    }
     // the 64-bit view of a mask may alias the 32-bit words it is built from
     typedef unsigned long long __attribute__((may_alias)) mask_t;
     const uint32_t half = (uint32_t)lane_id() >> 5, me = 1u << (lane_id() & 31);
@@ -486,6 +506,22 @@ __global__ __launch_bounds__(BT) void k_hist(Work w, int L) {
         const size_t g0 = (size_t)seg.begin + (size_t)(t - seg.tile_start) * w.tile_keys;
         const size_t g1 = (size_t)seg.begin + min((size_t)seg.len, (size_t)(te - seg.tile_start) * w.tile_keys);
         V a = KT::ones(), o = KT::zero();
+        // one-bit steps count with ballots: per wave step, the popcounts of
+        // the active lanes and of those whose bit is 1, added to the wave's
+        // counters by its first active lane (the loops below are divergent);
+        // wider digits with a per-wave LDS histogram
+        auto count = [&](const V &v) {
+            const uint32_t d = KT::digit(v, bitpos, wbits);
+            if constexpr (K == 1) {
+                const uint64_t act = __ballot(true), ones = __ballot(d != 0u);
+                if (lane == __builtin_ctzll(act)) {
+                    s_h[wv][1] += (uint32_t)__popcll(ones);
+                    s_h[wv][0] += (uint32_t)__popcll(act & ~ones);
+                }
+            } else {
+                atomicAdd(&s_h[wv][d], 1u);
+            }
+        };
         // head and tail one key at a time, the 16-byte aligned body 16 bytes at
         // a time (keys are at least key-size aligned, so `mis` is whole keys)
         const size_t mis = ((16u - (reinterpret_cast<uintptr_t>(src) & 15u)) & 15u) / KB;
@@ -494,14 +530,14 @@ __global__ __launch_bounds__(BT) void k_hist(Work w, int L) {
         for (size_t i = g0 + threadIdx.x; i < b0; i += BT) {
             const V v = ld_key<KB>(src, i, kind);
             if (i > seg.begin) desc |= key_after<KB>(ld_key<KB>(src, i - 1, kind), v, km, full);
-            atomicAdd(&s_h[wv][KT::digit(v, bitpos, wbits)], 1u);
+            count(v);
             a = KT::vand(a, v);
             o = KT::vor(o, v);
         }
         for (size_t i = b1 + threadIdx.x; i < g1; i += BT) {
             const V v = ld_key<KB>(src, i, kind);
             if (i > seg.begin) desc |= key_after<KB>(ld_key<KB>(src, i - 1, kind), v, km, full);
-            atomicAdd(&s_h[wv][KT::digit(v, bitpos, wbits)], 1u);
+            count(v);
             a = KT::vand(a, v);
             o = KT::vor(o, v);
         }
@@ -533,7 +569,7 @@ __global__ __launch_bounds__(BT) void k_hist(Work w, int L) {
                     for (int q = 1; q < VN; ++q) desc |= key_after<KB>(v[u][q - 1], v[u][q], km, full);
 #pragma unroll
                     for (int q = 0; q < VN; ++q) {
-                        atomicAdd(&s_h[wv][KT::digit(v[u][q], bitpos, wbits)], 1u);
+                        count(v[u][q]);
                         a = KT::vand(a, v[u][q]);
                         o = KT::vor(o, v[u][q]);
                     }
