@@ -447,7 +447,7 @@ __global__ __launch_bounds__(THREADS) void k_small_pairs(Work w, int L) {
     const uint32_t wave_id = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
     const uint32_t nwaves = gridDim.x * (blockDim.x / WAVE);
     const Canon km = canon_lead_mask((int)w.nbits);
-    unsigned long long st_keys = 0ull, st_segs = 0ull;
+    // (k_plan counts these children: per-wave counter atomics serialise)
     for (uint32_t e0 = wave_id * WAVE; e0 < npairs; e0 += nwaves * WAVE) {
         const uint32_t e = e0 + lane;
         uint32_t b = 0u, len = 0u;
@@ -461,9 +461,6 @@ __global__ __launch_bounds__(THREADS) void k_small_pairs(Work w, int L) {
                 if (b < seg.begin || b - seg.begin + c > seg.len) {
                     atomicOr(&ctl->error, ERR_INTERNAL);
                     len = 0u;
-                } else {
-                    st_keys += len;
-                    ++st_segs;
                 }
             }
         }
@@ -484,15 +481,6 @@ __global__ __launch_bounds__(THREADS) void k_small_pairs(Work w, int L) {
                 if constexpr (PAY) w.pay[0][eb + r] = pv;
             }
         });
-    }
-#pragma unroll
-    for (int o = 1; o < WAVE; o <<= 1) {
-        st_keys += __shfl_xor(st_keys, o, WAVE);
-        st_segs += __shfl_xor(st_segs, o, WAVE);
-    }
-    if (lane == 0 && st_segs) {
-        atomicAdd(&ctl->small_keys, st_keys);
-        atomicAdd(&ctl->small_segs, st_segs);
     }
 }
 

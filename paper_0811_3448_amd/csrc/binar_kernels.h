@@ -42,6 +42,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "binar_keys.h"
 
 namespace binar {
@@ -288,10 +290,42 @@ __device__ void block_append(const Work &w, int Lnext, int cat, uint32_t begin, 
     const uint32_t ntiles = (cat == NCLASS) ? (len + w.tile_keys - 1) / w.tile_keys : 0u;
     uint32_t tot_tiles;
     const uint32_t tidx = block_excl_scan(ntiles, s_tmp, &tot_tiles);
+    // the finish counters (keys and sub-arrays per class, and of the small
+    // path) are kept here, once per block: thousands of finishing waves or
+    // blocks adding to one address each would serialise
+    __shared__ uint32_t s_fk[NCLASS + 1][THREADS / WAVE];
+    uint32_t fkeys[NCLASS + 1];
+    {
+        const int wv = threadIdx.x / WAVE;
+#pragma unroll
+        for (int q = 0; q <= NCLASS; ++q) {
+            uint32_t x = (cat == (q < NCLASS ? q : CAT_SMALL)) ? len : 0u;
+#pragma unroll
+            for (int o = 1; o < WAVE; o <<= 1) x += __shfl_xor(x, o, WAVE);
+            if (lane_id() == 0) s_fk[q][wv] = x;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q <= NCLASS; ++q) {
+            fkeys[q] = 0u;
+#pragma unroll
+            for (int v = 0; v < THREADS / WAVE; ++v) fkeys[q] += s_fk[q][v];
+        }
+    }
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int q = 0; q < NCLASS; ++q) s_base[q] = tot[q] ? atomicAdd(&w.ctl->fin_ctr[q], tot[q]) : 0u;
+        for (int q = 0; q < NCLASS; ++q) {
+            s_base[q] = tot[q] ? atomicAdd(&w.ctl->fin_ctr[q], tot[q]) : 0u;
+            if (tot[q]) {
+                atomicAdd(&w.ctl->fin_keys[q], (unsigned long long)fkeys[q]);
+                atomicAdd(&w.ctl->fin_segs[q], (unsigned long long)tot[q]);
+            }
+        }
         s_base[NCLASS + 3] = tot[CAT_SMALL] ? atomicAdd(&w.ctl->small_ctr, tot[CAT_SMALL]) : 0u;
+        if (tot[CAT_SMALL]) {
+            atomicAdd(&w.ctl->small_keys, (unsigned long long)fkeys[NCLASS]);
+            atomicAdd(&w.ctl->small_segs, (unsigned long long)tot[CAT_SMALL]);
+        }
         if (tot[NCLASS]) {
             const unsigned long long old = atomicAdd(&w.ctl->list_ctr[Lnext],
                                                      ((unsigned long long)tot[NCLASS] << 32) | tot_tiles);
@@ -705,6 +739,7 @@ __global__ __launch_bounds__(THREADS) void k_plan(Work w, int L, int pass) {
     // statistics: summed per block, one atomic each at the end (per-segment
     // atomics on one address serialise the whole grid)
     unsigned long long st_hist = 0ull, st_moved = 0ull, st_sorted = 0ull;
+    unsigned long long st_small_keys = 0ull, st_small_segs = 0ull;  // in place: children ranked from the table
 
     for (uint32_t s = blockIdx.x; s < nslots; s += gridDim.x) {
         const SegEntry seg = w.list[L][s];
@@ -760,6 +795,14 @@ __global__ __launch_bounds__(THREADS) void k_plan(Work w, int L, int pass) {
 
         uint32_t total;
         const uint32_t excl = block_excl_scan(c, s_tmp, &total);
+        if (w.inplace) {
+            const bool small = c >= 2u && c <= SMALL_MAX;
+            uint32_t sk, sc;
+            (void)block_excl_scan(small ? c : 0u, s_tmp, &sk);
+            (void)block_excl_scan(small ? 1u : 0u, s_tmp, &sc);
+            st_small_keys += sk;
+            st_small_segs += sc;
+        }
         int cat = -1;
         uint32_t cb = 0;
         bool done = false;
@@ -806,6 +849,10 @@ __global__ __launch_bounds__(THREADS) void k_plan(Work w, int L, int pass) {
         if (st_hist) atomicAdd(&ctl->hist_keys[ps], st_hist);
         if (st_moved) atomicAdd(&ctl->moved[ps], st_moved);
         if (st_sorted) atomicAdd(&ctl->sorted_keys, st_sorted);
+        if (st_small_segs) {
+            atomicAdd(&ctl->small_keys, st_small_keys);
+            atomicAdd(&ctl->small_segs, st_small_segs);
+        }
     }
 }
 
@@ -1598,7 +1645,6 @@ void k_finish(Work w, int cls) {
     for (int i = threadIdx.x; i < NW * 2 * R; i += BT) (&S.tbl[0][0])[i] = 0u;
     __syncthreads();
 
-    unsigned long long st_keys = 0ull, st_segs = 0ull;  // flushed once per block
     constexpr int NVK = (CAP + Vec<KB>::N * BT - 1) / (Vec<KB>::N * BT);
     constexpr int NVP = (CAP + 4 * BT - 1) / (4 * BT);
     for (uint32_t f = blockIdx.x; f < nfin; f += gridDim.x) {
@@ -1610,8 +1656,6 @@ void k_finish(Work w, int cls) {
             if (threadIdx.x == 0) atomicOr(&ctl->error, ERR_INTERNAL);
             continue;
         }
-        st_keys += len;
-        ++st_segs;
         // load into LDS in input order, AND/OR on the way
         V a = KT::ones(), o = KT::zero();
         fin_load_keys<KB, NVK, BT>(w.keys[parity], fe.begin, (size_t)fe.begin + len, S.keys, a, o, w.kind);
@@ -1665,10 +1709,6 @@ void k_finish(Work w, int cls) {
         if constexpr (PAY) fin_store_pay<BT>(w.pay[0], fe.begin, (size_t)fe.begin + len, S.pay);
         __syncthreads();
     }
-    if (threadIdx.x == 0 && st_segs) {
-        atomicAdd(&ctl->fin_keys[cls], st_keys);
-        atomicAdd(&ctl->fin_segs[cls], st_segs);
-    }
 }
 
 // ----------------------------------------------------------- k_finish_wave
@@ -1694,7 +1734,7 @@ struct WaveFinLds {
 
 // Stable passes over the varying bits in [bitpos, end] of the wave's slice,
 // least significant window of up to 8 bits first.
-template <int KB, bool PAY>
+template <int KB, bool PAY, int IT>
 __device__ __forceinline__ void wave_passes(WaveFinLds<KB, PAY> &S, Canon diff, int bitpos, int end, uint32_t len) {
     using KT = KeyT<KB>;
     using V = typename KT::V;
@@ -1704,17 +1744,17 @@ __device__ __forceinline__ void wave_passes(WaveFinLds<KB, PAY> &S, Canon diff, 
     while (hib >= bitpos) {
         const int lo = max(bitpos, hib - 7);
         const int wbits = hib - lo + 1;
-        V key[FW_ITEMS];
-        uint32_t dg[FW_ITEMS], rnk[FW_ITEMS], pv[FW_ITEMS];
+        V key[IT];
+        uint32_t dg[IT], rnk[IT], pv[IT];
 #pragma unroll
-        for (int j = 0; j < FW_ITEMS; ++j) {
+        for (int j = 0; j < IT; ++j) {
             const uint32_t e = (uint32_t)lane + j * WAVE;
             key[j] = (e < len) ? S.keys[e] : KT::zero();
             dg[j] = KT::digit(key[j], lo, wbits);
         }
-        wave_rank<R, RANK_GROUP, FW_ITEMS, false>(dg, (uint32_t)lane, len, S.tbl, S.wh, rnk);
+        wave_rank<R, RANK_GROUP, IT, false>(dg, (uint32_t)lane, len, S.tbl, S.wh, rnk);
 #pragma unroll
-        for (int j = 0; j < FW_ITEMS; ++j) {
+        for (int j = 0; j < IT; ++j) {
             const uint32_t e = (uint32_t)lane + j * WAVE;
             pv[j] = (PAY && e < len) ? S.pay[e] : 0u;
         }
@@ -1736,7 +1776,7 @@ __device__ __forceinline__ void wave_passes(WaveFinLds<KB, PAY> &S, Canon diff, 
             S.wh[4 * lane + 3] = b + c0 + c1 + c2;
         }
 #pragma unroll
-        for (int j = 0; j < FW_ITEMS; ++j) {
+        for (int j = 0; j < IT; ++j) {
             const uint32_t e = (uint32_t)lane + j * WAVE;
             if (e < len) {
                 const uint32_t pos = S.wh[dg[j]] + rnk[j];
@@ -1752,7 +1792,7 @@ __device__ __forceinline__ void wave_passes(WaveFinLds<KB, PAY> &S, Canon diff, 
 // Tied runs of the wave's slice after sorting by bits [0, pe]: runs of up to
 // 64 keys ranked in the wave on the leading nb bits (packed, as in
 // fix_runs); true, with nothing of a longer run moved, if a run is longer.
-template <int KB, bool PAY>
+template <int KB, bool PAY, int IT>
 __device__ bool wave_fix_runs(WaveFinLds<KB, PAY> &S, int pe, uint32_t len, int nb) {
     using KT = KeyT<KB>;
     using V = typename KT::V;
@@ -1768,7 +1808,7 @@ __device__ bool wave_fix_runs(WaveFinLds<KB, PAY> &S, int pe, uint32_t len, int 
     // run starts in position order (position = lane + 64 j)
     uint32_t nruns = 0;
 #pragma unroll
-    for (int j = 0; j < FW_ITEMS; ++j) {
+    for (int j = 0; j < IT; ++j) {
         const uint32_t p = (uint32_t)lane + j * WAVE;
         bool st = false;
         if (p + 1 < len) {
@@ -1835,7 +1875,6 @@ __global__ __launch_bounds__(FinWaves<KB>::n * WAVE) void k_finish_wave(Work w, 
     for (int i = lane; i < 2 * 256; i += WAVE) S.tbl[i] = 0u;
     for (int i = lane; i < 256; i += WAVE) S.wh[i] = 0u;
     const uint32_t gw = blockIdx.x * NWB + wv, nw = gridDim.x * NWB;
-    unsigned long long st_keys = 0ull, st_segs = 0ull;
     for (uint32_t f = gw; f < nfin; f += nw) {
         const FinEntry fe = uni(w.fin[cls][f]);
         const uint32_t len = fe.info & 0xFFFFu;
@@ -1845,8 +1884,6 @@ __global__ __launch_bounds__(FinWaves<KB>::n * WAVE) void k_finish_wave(Work w, 
             if (lane == 0) atomicOr(&ctl->error, ERR_INTERNAL);
             continue;
         }
-        st_keys += len;
-        ++st_segs;
         V a = KT::ones(), o = KT::zero();
         for (uint32_t p = lane; p < len; p += WAVE) {
             const V k = ld_key<KB>(w.keys[parity], (size_t)fe.begin + p, w.kind);
@@ -1870,17 +1907,26 @@ __global__ __launch_bounds__(FinWaves<KB>::n * WAVE) void k_finish_wave(Work w, 
             const int fb = first_set_from(diff, bitpos, NB);
             const int f2 = first_set_from(diff, min(fb + 8, NB), NB);
             const int pe = (f2 >= NB) ? lb : min(lb, f2 + 7);
-            wave_passes<KB, PAY>(S, diff, bitpos, pe, len);
-            if (pe < lb && wave_fix_runs<KB, PAY>(S, pe, len, NB)) wave_passes<KB, PAY>(S, diff, bitpos, lb, len);
+            // loops sized to the sub-array: 2, 4, 8 or 16 keys per lane
+            auto sort_it = [&](auto it) {
+                constexpr int IT = decltype(it)::value;
+                wave_passes<KB, PAY, IT>(S, diff, bitpos, pe, len);
+                if (pe < lb && wave_fix_runs<KB, PAY, IT>(S, pe, len, NB))
+                    wave_passes<KB, PAY, IT>(S, diff, bitpos, lb, len);
+            };
+            if (len <= 2u * WAVE)
+                sort_it(std::integral_constant<int, 2>());
+            else if (len <= 4u * WAVE)
+                sort_it(std::integral_constant<int, 4>());
+            else if (len <= 8u * WAVE)
+                sort_it(std::integral_constant<int, 8>());
+            else
+                sort_it(std::integral_constant<int, FW_ITEMS>());
         }
         for (uint32_t p = lane; p < len; p += WAVE) {
             KT::store(w.keys[0], (size_t)fe.begin + p, raw_key<KB>(S.keys[p], w.kind));
             if (PAY) w.pay[0][fe.begin + p] = S.pay[p];
         }
-    }
-    if (lane == 0 && st_segs) {
-        atomicAdd(&ctl->fin_keys[cls], st_keys);
-        atomicAdd(&ctl->fin_segs[cls], st_segs);
     }
 }
 
@@ -1904,11 +1950,16 @@ __global__ __launch_bounds__(THREADS) void k_finish_small(Work w) {
     const uint32_t wave_id = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
     const uint32_t nwaves = gridDim.x * (blockDim.x / WAVE);
     const Canon km = canon_lead_mask((int)w.nbits);
-    unsigned long long st_keys = 0ull, st_segs = 0ull;  // per lane, reduced at the end
-    for (uint32_t e0 = wave_id * WAVE; e0 < nent; e0 += nwaves * WAVE) {
-        // lane l holds entry e0 + l
+    // entries per wave: about 256 keys' worth (four packed rounds), from the
+    // bound n_total / entries on their mean length -- pairs fill a window
+    // of 64, sub-arrays of 60 keys get one entry per wave instead of 64
+    // serial rounds on a few waves
+    const unsigned long long wfit = (256ull * nent) / (w.n_total ? w.n_total : 1u);
+    const uint32_t win = wfit >= (unsigned long long)WAVE ? (uint32_t)WAVE : (wfit ? (uint32_t)wfit : 1u);
+    for (uint32_t e0 = wave_id * win; e0 < nent; e0 += nwaves * win) {
+        // lane l < win holds entry e0 + l
         uint32_t b = 0u, len = 0u, par = 0u;
-        if (e0 + lane < nent) {
+        if ((uint32_t)lane < win && e0 + lane < nent) {
             const FinEntry fe = w.fin_small[e0 + lane];
             b = fe.begin;
             len = fe.info & 0xFFFFu;
@@ -1917,8 +1968,6 @@ __global__ __launch_bounds__(THREADS) void k_finish_small(Work w) {
                 atomicOr(&ctl->error, ERR_INTERNAL);
                 len = 0u;
             }
-            st_keys += len;
-            ++st_segs;
         }
         wave_pack(len, [&](int l, uint32_t i, int head, bool act, uint32_t el, uint32_t ml) {
             const uint32_t eb = __shfl(b, l, WAVE), ep = __shfl(par, l, WAVE);
@@ -1937,15 +1986,6 @@ __global__ __launch_bounds__(THREADS) void k_finish_small(Work w) {
                 if constexpr (PAY) w.pay[0][eb + r] = pv;
             }
         });
-    }
-#pragma unroll
-    for (int o = 1; o < WAVE; o <<= 1) {
-        st_keys += __shfl_xor(st_keys, o, WAVE);
-        st_segs += __shfl_xor(st_segs, o, WAVE);
-    }
-    if (lane == 0 && st_segs) {
-        atomicAdd(&ctl->small_keys, st_keys);
-        atomicAdd(&ctl->small_segs, st_segs);
     }
 }
 
