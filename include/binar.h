@@ -13,9 +13,11 @@
  * continue on every sub-array with the next bits, stopping when a sub-array
  * has one element or the bits are used up.  Here every partition is stable,
  * k bits are taken per pass (a stable 2^k-way partition is k stable binary
- * partitions in a row), all live sub-arrays are partitioned in one
- * breadth-first pass, and sub-arrays small enough for on-chip memory are
- * finished by one workgroup each.
+ * partitions in a row; a one-bit step ranks with wavefront ballots), all
+ * live sub-arrays are partitioned in one breadth-first pass, and sub-arrays
+ * small enough for on-chip memory (LDS) are finished there: by a
+ * workgroup, by one wavefront (up to 1024 keys), or packed many to a
+ * wavefront (up to 64 keys).
  *
  * Key views (section "The Other Universal Property": the encoding is what
  * is sorted):
