@@ -127,3 +127,33 @@ def test_small_kinds(kind):
     gk, gp = gpu_sort_segmented(keys, off, pay, params=P(key_kind=kind))
     rk, rp = orders.sort_segmented(keys, off, pay, kind)
     assert np.array_equal(gp, rp) and np.array_equal(gk, rk)
+
+
+@pytest.mark.parametrize("kb", [4, 8, 16])
+def test_wave_finish_long_tied_runs(kb):
+    """Sub-arrays of 65..1024 keys (one wave each for 4- and 8-byte keys)
+    whose keys share their leading varying bits in two or three long runs:
+    the ranking of tied runs gives way to passes over every varying bit.
+    Full-key ties too (stability)."""
+    rng = np.random.default_rng(980 + kb)
+    lens = rng.integers(65, 1025, 300)
+    off = np.zeros(lens.shape[0] + 1, dtype=np.uint32)
+    off[1:] = np.cumsum(lens)
+    n = int(off[-1])
+    seg = np.repeat(np.arange(lens.shape[0]), lens)
+    leads = rng.integers(0, 1 << 16, (lens.shape[0], 3), dtype=np.uint64)
+    lead = leads[seg, rng.integers(0, 3, n)]
+    low = rng.integers(0, 1 << 20, n, dtype=np.uint64)
+    low[rng.random(n) < 0.2] = 5
+    if kb == 4:
+        keys = ((lead << np.uint64(16)) | (low & np.uint64(0xFFFF))).astype(np.uint32)
+    elif kb == 8:
+        keys = ((lead << np.uint64(48)) | low).astype(np.uint64)
+    else:
+        words = np.stack([(lead << np.uint64(48)) | low, low * np.uint64(0x9E3779B97F4A7C15)], axis=1)
+        keys = words.astype(">u8").view(np.uint8).reshape(n, 16).copy()
+    print("wave finish long runs kb=%d n=%d" % (kb, n), flush=True)
+    gk, gp = gpu_sort_segmented(keys, off, iota(n))
+    rk, rp = oracle.sort_segmented(keys, off, iota(n))
+    assert np.array_equal(gk, rk)
+    assert np.array_equal(gp, rp)
