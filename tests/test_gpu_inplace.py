@@ -149,3 +149,15 @@ def test_digit_4_partial_and_kinds():
     gk, gp, _ = ip_sort(ik, pay, params=P(key_kind=orders.SIGNED, digit_bits=4))
     rk, rp = orders.sort(ik, pay, orders.SIGNED)
     assert np.array_equal(gp, rp) and np.array_equal(gk, rk)
+
+
+@pytest.mark.parametrize("nbits", [12, 40, 100])
+def test_partial_bits_16_bytes(nbits):
+    """16-byte keys in place, sorted by their leading nbits bits only (the
+    walk's digits come from the leading bits of each key's first bytes)."""
+    n = 150_001
+    keys = workloads.str16(n, 780 + nbits, 3)
+    pay = np.arange(n, dtype=np.uint32)
+    gk, gp, _ = ip_sort(keys, pay, params=P(key_bits=nbits))
+    rk, rp = oracle.partition(keys, pay, nbits)
+    assert np.array_equal(gp, rp) and np.array_equal(gk, rk)
