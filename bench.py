@@ -583,13 +583,19 @@ def main() -> int:
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
+    # one event between consecutive sorts (same stream, no sync): per-step
+    # times for the median / min / max beside the total
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
     t0 = time.perf_counter()
     ev0.record(stream)
+    marks[0].record(stream)
     for i in range(W, W + K):
         sort_fn(bufs[i][0], bufs[i][1], workspace=ws, params=params)
+        marks[i - W + 1].record(stream)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    step_ms = sorted(marks[j].elapsed_time(marks[j + 1]) for j in range(K))
     launches = binar.profile_read()
     binar.profile_enable(False)
     gpu_ms = ev0.elapsed_time(ev1)
@@ -668,6 +674,7 @@ def main() -> int:
         "steps": K,
         "warmup": W,
         "ms_per_step": round(ms_per_step, 4),
+        "step_ms": {"median": round(step_ms[K // 2], 4), "min": round(step_ms[0], 4), "max": round(step_ms[-1], 4)},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
