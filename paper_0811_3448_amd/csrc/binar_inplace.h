@@ -15,10 +15,13 @@
 //             digit), in a table that takes the place of the piece prefixes
 //             it was computed from.
 //   k_cycle   applies the permutation  i -> i + dist[tile(i)][digit(key i)]
-//             by following its cycles: each lane carries one key to its
-//             place, picks up the key found there and carries that one on.
-//             One claim bit per position makes every key picked up exactly
-//             once and every place written exactly once.
+//             by following its cycles: a walk carries one key to its place,
+//             picks up the key found there and carries that one on (a lane
+//             runs several walks side by side).  One claim bit per position
+//             makes every key picked up exactly once and every place
+//             written exactly once.  With 4-bit digits a tile's runs are
+//             long, so neighbouring walks stay together and their accesses
+//             coalesce.
 //   k_small_pairs  children of 2..SMALL_MAX keys, read straight from the
 //             pass's count table and ranked inside a wave (no list).
 //
@@ -35,7 +38,7 @@ namespace binar {
 
 constexpr uint32_t IP_GRANULE = 256;     // positions per entry of the segment map
 constexpr uint32_t IP_NONE = 0xFFFFFFFFu;
-// digit bits of the in-place passes: 4 or 8 (K below)
+// digit bits of the in-place passes: 4 or 8 (template parameter K)
 constexpr int IP_BT = 512, IP_ITEMS = 8;  // one tile = 4096 keys
 constexpr uint32_t IP_TILE = IP_BT * IP_ITEMS;
 
