@@ -103,6 +103,23 @@ __global__ __launch_bounds__(IP_BT) void k_local(Work w, int L, IpMaps m) {
     uint32_t seg_end = uni(seg_tile_end(w.list[L], slot, nslots, ntiles));
     bool entered = false;
     const uint32_t ebase = (uint32_t)wv * IP_ITEMS * WAVE + (uint32_t)lane;
+    // the next tile of the same segment is loaded (as stored) while the
+    // current one is sorted; tiles are disjoint, so its loads may still be
+    // in flight while the current tile is written back
+    V kn[IP_ITEMS];
+    uint32_t pn[IP_ITEMS];
+    bool have_next = false;
+    auto load_raw = [&](uint32_t tt, V (&kk)[IP_ITEMS], uint32_t (&pp)[IP_ITEMS]) {
+        const uint32_t o = (tt - seg.tile_start) * IP_TILE;
+        const uint32_t ln = min(IP_TILE, seg.len - o);
+        const uint32_t b0 = seg.begin + o;
+#pragma unroll
+        for (int j = 0; j < IP_ITEMS; ++j) {
+            const uint32_t e = ebase + j * WAVE;
+            kk[j] = (e < ln) ? KT::load(w.keys[0], (size_t)b0 + e) : KT::zero();
+            pp[j] = (PAY && e < ln) ? w.pay[0][b0 + e] : 0u;
+        }
+    };
     while (t < t1) {
         if (!entered) {
             if (((seg.info >> 16) & SEG_SKIP) || ((seg.info >> 8) & 1u)) {
@@ -133,11 +150,20 @@ __global__ __launch_bounds__(IP_BT) void k_local(Work w, int L, IpMaps m) {
         }
         V key[IP_ITEMS];
         uint32_t pay[IP_ITEMS], dg[IP_ITEMS], rnk[IP_ITEMS];
+        if (have_next) {
+#pragma unroll
+            for (int j = 0; j < IP_ITEMS; ++j) {
+                key[j] = kn[j];
+                pay[j] = pn[j];
+            }
+        } else {
+            load_raw(t, key, pay);
+        }
+        have_next = t + 1 < t1 && t + 1 < seg_end && (size_t)seg.begin + seg.len <= w.n_total;
+        if (have_next) load_raw(t + 1, kn, pn);
 #pragma unroll
         for (int j = 0; j < IP_ITEMS; ++j) {
-            const uint32_t e = ebase + j * WAVE;
-            key[j] = (e < tlen) ? ld_key<KB>(w.keys[0], (size_t)tb + e, w.kind) : KT::zero();
-            pay[j] = (PAY && e < tlen) ? w.pay[0][tb + e] : 0u;
+            if (w.kind) key[j] = KT::enc(key[j], w.kind);
             dg[j] = KT::digit(key[j], bitpos, wbits);
         }
         wave_rank<R, RANK_GROUP, IP_ITEMS, false>(dg, ebase, tlen, &S.tbl[wv][0], &S.wh[wv][0], rnk);
