@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libbinar.so")
 SOURCES = [os.path.join(HERE, "csrc", "binar_api.hip")]
-DEPS = SOURCES + [os.path.join(HERE, "csrc", f) for f in ("binar_kernels.h", "binar_keys.h")] + [
+DEPS = SOURCES + [os.path.join(HERE, "csrc", f) for f in ("binar_kernels.h", "binar_keys.h", "binar_inplace.h", "binar_strings.h")] + [
     os.path.join(ROOT, "include", "binar.h")]
 
 HIPCC_FLAGS = [
