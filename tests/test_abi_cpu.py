@@ -128,3 +128,14 @@ def test_strings_argument_errors(lib):
     assert lib.binar_sort_strings(vp(0x10000), 10, None, 5, vp(0x20000), None, None, 0) == -1  # NULL offsets
     assert lib.binar_sort_strings(vp(0x10000), 10, vp(0x20000), 5, None, None, None, 0) == -1  # NULL payload
     assert lib.binar_sort_strings(vp(0x10000), 10, vp(0x20000), 1 << 30, vp(0x30000), None, None, 0) == -2
+
+
+def test_build_tracks_every_source():
+    """The library is rebuilt when any of its sources changes: every file
+    under csrc and the public header are dependencies of the build."""
+    from paper_0811_3448_amd import build
+    csrc = os.path.join(os.path.dirname(build.__file__), "csrc")
+    deps = {os.path.abspath(p) for p in build.DEPS}
+    for f in os.listdir(csrc):
+        assert os.path.abspath(os.path.join(csrc, f)) in deps, f
+    assert any(p.endswith(os.path.join("include", "binar.h")) for p in deps)
