@@ -78,7 +78,8 @@ def test_full_size(name):
         assert k == keys[j] and p == j, "input %d should sit at output %d" % (j, r)
 
 
-@pytest.mark.parametrize("name", ["u32_2e28_uniform", "u64_2e27_uniform", "u64_2e27_zipf"])
+@pytest.mark.parametrize("name", ["u32_2e28_uniform", "u32_2e28_and4", "u32_2e28_dup256", "u64_2e27_uniform",
+                                  "u64_2e27_nearly_sorted", "u64_2e27_zipf"])
 def test_full_size_inplace(name):
     """The in-place variant at full size, in the configuration
     `bench.py --inplace` times (library defaults: 4-bit digits)."""
