@@ -32,7 +32,9 @@ CSRC = os.path.join(ROOT, "paper_0811_3448_amd", "csrc")
 
 # the sources the fixed-width sort's kernels and launches are built from
 # (the string and in-place paths live in files of their own)
-TRAFFIC_SOURCES = ("binar_api.hip", "binar_keys.h", "binar_kernels.h")
+TRAFFIC_SOURCES = ("binar_api.hip", "binar_host.h", "binar_keys.h", "binar_kernels.h", "binar_launch_4p.hip",
+                   "binar_launch_4k.hip", "binar_launch_8p.hip", "binar_launch_8k.hip", "binar_launch_16p.hip",
+                   "binar_launch_16k.hip")
 
 
 def kernel_source_hash() -> str:

@@ -209,9 +209,10 @@ int binar_profile_read(binar_launch_time *out, uint32_t cap, uint32_t *count);
  * the buffers then hold (segment offsets are read on the device, so the
  * segment layout may change between replays within the capacity).  Up to 16
  * graphs are kept per plan.  With seg_offsets, keys and payload must hold
- * max_keys entries (the offsets are checked on the device against max_keys
- * and n_total is ignored), so one graph serves every batch placed in the
- * same buffers.  seg_offsets may be NULL: one array of n_total keys (then
+ * max_keys entries and n_total is their length: a call with n_total below
+ * max_keys returns BINAR_EINVAL before any device work (the offsets are
+ * checked on the device against max_keys), so one graph serves every batch
+ * placed in the same buffers.  seg_offsets may be NULL: one array of n_total keys (then
  * n_total is part of the graph's identity).  Calls on one plan must not
  * overlap in time.  binar_plan_stats reads
  * the counters of the plan's last sort; binar_plan_graphs returns how many

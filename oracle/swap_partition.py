@@ -1,60 +1,65 @@
 """The paper's own in-place exchange partition -- TEST INFRASTRUCTURE ONLY.
 
-Written from the prose of section "Operation of Algorithm": the element at
-the lower position is the working element; its bit (section "Bit
-Extraction", bit 0 = most significant) either leaves it in the lower
-sub-array (lower bound moves up) or exchanges it with the element at the
-upper bound (upper bound moves down), until the bounds cross (section
-"Partition Repetition").  If every element stayed low the call continues on
-the same bounds with the next bit ("pass-through"); otherwise it continues on
-both sub-arrays (section "Determine Recursive Call on Sub-arrays").  The
-recursion stops at one element or when the bits are used up (section
-"Evaluate for Recursive Base Case").
+Restated from the prose of section "Operation of Algorithm" and section
+"Partition Repetition": a sub-array is split on one bit (section "Bit
+Extraction", bit 0 = most significant) by moving a front cursor up over
+elements whose bit is 0, and sending each element whose bit is 1 to the back,
+where it changes places with the element that stood there; the back boundary
+then moves down and the element that arrived is examined next.  When the two
+cursors meet, the front part holds the 0s and the back part the 1s.  If one
+part is empty the same bounds continue with the next bit (pass-through,
+section "Optimize the Algorithm"); otherwise both parts continue with the
+next bit (section "Determine Recursive Call on Sub-arrays").  A part of one
+element, or a bit index past the key width, is finished (section "Evaluate
+for Recursive Base Case").
 
-The exchange makes this partition unstable (section "Conclusion"); it serves
-only to check the paper's printed configurations and that its key order
-agrees with the stable oracle.
+Here the recursion is an explicit work stack of half-open ranges.  The
+exchange makes the partition unstable (section "Conclusion"); this module
+serves only to check the paper's printed configurations and that its key
+order agrees with the stable oracle.
 """
 from __future__ import annotations
-
-
-def _bit(value: int, width: int, b: int) -> int:
-    return (value >> (width - 1 - b)) & 1
 
 
 def binar_swap_sort(values: list[int], width: int, trace=None, payload=None) -> list[int]:
     """Sort a list of ``width``-bit unsigned integers in place, unstably.
 
-    ``payload`` (optional list) is exchanged along with the values.
+    ``payload`` (optional list) changes places along with the values.
 
-    ``trace`` (optional list) receives, for each partition call, a record
-    ``(bit, lower, upper, states)`` where ``states`` lists the configuration
-    (lower sub-array, unplaced, upper sub-array) before the first placement
-    and after each placement.
+    ``trace`` (optional list) receives one record per split,
+    ``(bit, first, last, states)`` with inclusive bounds ``first..last`` as
+    the paper prints them, where ``states`` lists the configuration (0s
+    placed, not yet examined, 1s placed) before the first step and after
+    every step.
     """
     a = values
+    shift = [width - 1 - b for b in range(width)]
 
-    def rec(lower: int, upper: int, b: int) -> None:  # inclusive bounds
-        if b >= width or upper < lower + 1:
-            return
-        lo, hi = lower, upper
-        states = [(a[lower:lo], a[lo:hi + 1], a[hi + 1:upper + 1])]
-        while lo <= hi:
-            if _bit(a[lo], width, b) == 0:
-                lo += 1
+    def exchange(i: int, j: int) -> None:
+        a[i], a[j] = a[j], a[i]
+        if payload is not None:
+            payload[i], payload[j] = payload[j], payload[i]
+
+    work = [(0, len(a), 0)]                # (start, stop exclusive, bit)
+    while work:
+        start, stop, bit = work.pop()
+        if stop - start < 2 or bit >= width:
+            continue
+        front, back = start, stop           # [start, front) holds 0s, [back, stop) holds 1s
+        snap = lambda: (a[start:front], a[front:back], a[back:stop])  # noqa: E731
+        states = [snap()]
+        while front != back:
+            if (a[front] >> shift[bit]) & 1:
+                back -= 1
+                exchange(front, back)
             else:
-                a[lo], a[hi] = a[hi], a[lo]
-                if payload is not None:
-                    payload[lo], payload[hi] = payload[hi], payload[lo]
-                hi -= 1
-            states.append((a[lower:lo], a[lo:hi + 1], a[hi + 1:upper + 1]))
+                front += 1
+            states.append(snap())
         if trace is not None:
-            trace.append((b, lower, upper, [tuple(list(s) for s in st) for st in states]))
-        if lo == upper + 1:
-            rec(lower, upper, b + 1)
+            trace.append((bit, start, stop - 1, [tuple(list(part) for part in st) for st in states]))
+        if front in (start, stop):
+            work.append((start, stop, bit + 1))       # one side empty: same bounds, next bit
         else:
-            rec(lower, lo - 1, b + 1)
-            rec(lo, upper, b + 1)
-
-    rec(0, len(a) - 1, 0)
+            work.append((front, stop, bit + 1))       # the 1s, taken after
+            work.append((start, front, bit + 1))      # the 0s, taken first
     return a

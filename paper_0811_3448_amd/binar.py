@@ -358,15 +358,24 @@ class Plan:
         self.key_bytes, self.max_keys, self.max_segments = key_bytes, max_keys, max_segments
 
     def sort(self, keys, payload=None, seg_offsets=None, n_total: int | None = None, stream=None):
+        """Sort on the plan's graph.  Single array (seg_offsets None): n_total
+        keys (default: all of keys).  Segmented: keys and payload must hold the
+        plan's max_keys entries; n_total is then ignored."""
         _check_tensors(keys, payload)
         if key_bytes_of(keys) != self.key_bytes:
             raise ValueError("key width differs from the plan's")
         n = keys.shape[0] if n_total is None else n_total
         nseg = 0
         if seg_offsets is not None:
+            # segmented: the buffers must hold the plan's whole capacity (the
+            # device checks the offsets against it, not against n_total)
+            if keys.shape[0] < self.max_keys:
+                raise ValueError("segmented plan sort: keys hold %d entries, the plan's capacity is %d"
+                                 % (keys.shape[0], self.max_keys))
             if not seg_offsets.is_cuda or seg_offsets.element_size() != 4 or not seg_offsets.is_contiguous():
                 raise ValueError("seg_offsets must be a contiguous 4-byte device tensor")
             nseg = seg_offsets.shape[0] - 1
+            n = keys.shape[0]
         _check(lib.binar_plan_sort(self._h, _dev_ptr(keys), _dev_ptr(payload), _dev_ptr(seg_offsets), nseg, n,
                                    _stream_ptr(stream)))
         return keys

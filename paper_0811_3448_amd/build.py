@@ -1,22 +1,30 @@
-"""Build libbinar.so (the gfx950 HIP library) in-tree with hipcc."""
+"""Build libbinar.so (the gfx950 HIP library) in-tree with hipcc.
+
+The host code is split into translation units (the API, and the launch
+sequences of each key width with and without payload) that compile in parallel, then link into one
+shared library."""
 from __future__ import annotations
 
 import os
 import subprocess
 import sys
+import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbinar.so")
-SOURCES = [os.path.join(HERE, "csrc", "binar_api.hip")]
-DEPS = SOURCES + [os.path.join(HERE, "csrc", f) for f in ("binar_kernels.h", "binar_keys.h", "binar_inplace.h", "binar_strings.h")] + [
-    os.path.join(ROOT, "include", "binar.h")]
+SOURCES = [os.path.join(CSRC, f) for f in
+           ["binar_api.hip"] + ["binar_launch_%d%s.hip" % (kb, t) for kb in (4, 8, 16) for t in "pk"]]
+HEADERS = [os.path.join(CSRC, f) for f in
+           ("binar_host.h", "binar_kernels.h", "binar_keys.h", "binar_inplace.h", "binar_strings.h")]
+DEPS = SOURCES + HEADERS + [os.path.join(ROOT, "include", "binar.h")]
 
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # packed fp32 instructions stay off (no float math here, but keep the rule)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
+    "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
 
 
@@ -27,16 +35,33 @@ def stale() -> bool:
     return any(os.path.getmtime(p) > t for p in DEPS)
 
 
+def _filter(text: str) -> str:
+    return "\n".join(l for l in text.splitlines() if "packed-fp32-ops" not in l)
+
+
 def build(force: bool = True) -> str:
     if not force and not stale():
         return LIB
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc] + HIPCC_FLAGS + ["-o", tmp] + SOURCES
-    proc = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
-    out = "\n".join(l for l in proc.stdout.splitlines() if "packed-fp32-ops" not in l)
-    if proc.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + out)
+    with tempfile.TemporaryDirectory(prefix="binar_build_") as tmpdir:
+        objs, procs = [], []
+        for src in SOURCES:
+            obj = os.path.join(tmpdir, os.path.basename(src) + ".o")
+            objs.append(obj)
+            procs.append((src, subprocess.Popen([hipcc] + HIPCC_FLAGS + ["-c", "-o", obj, src],
+                                                stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
+        errors = []
+        for src, p in procs:
+            out, _ = p.communicate()
+            if p.returncode != 0:
+                errors.append("%s:\n%s" % (os.path.basename(src), _filter(out)))
+        if errors:
+            raise RuntimeError("hipcc failed:\n" + "\n".join(errors))
+        tmp = LIB + ".tmp%d" % os.getpid()
+        proc = subprocess.run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs,
+                              stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+        if proc.returncode != 0:
+            raise RuntimeError("hipcc link failed:\n" + _filter(proc.stdout))
     os.replace(tmp, LIB)
     return LIB
 

@@ -55,7 +55,7 @@ struct IpMaps {
 };
 
 // Clear the state bits and the segment map before a pass.
-__global__ __launch_bounds__(THREADS) void k_ip_clear(IpMaps m, uint32_t nstate, uint32_t nmap) {
+static __global__ __launch_bounds__(THREADS) void k_ip_clear(IpMaps m, uint32_t nstate, uint32_t nmap) {
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nstate; i += stride) m.state[i] = 0u;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nmap; i += stride)

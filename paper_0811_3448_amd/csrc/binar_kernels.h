@@ -269,7 +269,7 @@ __device__ __forceinline__ void wave_rank(const uint32_t (&dg)[ITEMS], uint32_t 
 }
 
 // ------------------------------------------------------------------ k_reset
-__global__ void k_reset(Ctl *ctl) {
+static __global__ void k_reset(Ctl *ctl) {
     uint32_t *p = reinterpret_cast<uint32_t *>(ctl);
     for (uint32_t i = threadIdx.x; i < sizeof(Ctl) / 4; i += blockDim.x) p[i] = 0u;
 }

@@ -127,7 +127,7 @@ class DeviceTimer:
             self.pay.copy_(self.pay0)
 
     def __call__(self, params: Params) -> float:
-        from .binar import Plan, Workspace, sort
+        from .binar import Plan, Workspace, sort, stats
         torch = self.torch
         if self.batched:
             plan = Plan(self.key_bytes, self.n, self.nseg, self.has_payload, params)
@@ -147,10 +147,51 @@ class DeviceTimer:
             e1.synchronize()
             if i >= self.warmup:
                 times.append(e0.elapsed_time(e1))
+        # a configuration whose kernels bailed out (wait limit, list overflow)
+        # returns early and would time as the fastest: read the device status
+        # and check the last output (outside the timed calls) before trusting
+        # the time
+        st = plan.stats() if self.batched else stats(ws)
+        ok = st["status"] == 0 and self._output_ok()
         if self.batched:
             plan.close()
+        if not ok:
+            return math.inf
         times.sort()
         return times[len(times) // 2]
+
+    def _output_ok(self) -> bool:
+        """The last sort's output is a sort of the input: keys nondecreasing
+        inside every segment, payload a permutation that carries the keys."""
+        torch = self.torch
+        k = self.keys
+        if self.key_bytes == 16:
+            be = k.to(torch.int64)
+            hi = torch.zeros(k.shape[0], dtype=torch.int64, device=k.device)
+            lo = torch.zeros_like(hi)
+            for b in range(8):
+                hi = (hi << 8) | be[:, b]
+                lo = (lo << 8) | be[:, 8 + b]
+            hi, lo = hi ^ (-(1 << 63)), lo ^ (-(1 << 63))     # unsigned order as signed
+            bad = (hi[1:] < hi[:-1]) | ((hi[1:] == hi[:-1]) & (lo[1:] < lo[:-1]))
+        elif self.key_bytes == 8:
+            u = k ^ (-(1 << 63))
+            bad = u[1:] < u[:-1]
+        else:
+            u = k.to(torch.int64) & 0xFFFFFFFF
+            bad = u[1:] < u[:-1]
+        if self.off is not None:
+            cut = self.off.to(torch.int64)
+            cut = cut[(cut > 0) & (cut < k.shape[0])] - 1       # pair (i, i+1) crosses a segment end
+            bad[cut] = False
+        if bool(bad.any().item()):
+            return False
+        if self.pay is None:
+            return True
+        p = self.pay.to(torch.int64)
+        if not torch.equal(torch.sort(p).values, torch.arange(p.shape[0], device=p.device)):
+            return False
+        return bool(torch.equal(self.pristine[p], k))
 
 
 def autotune(key_bytes: int, has_payload: bool, n: int, batched: bool = False,
@@ -167,11 +208,17 @@ def autotune(key_bytes: int, has_payload: bool, n: int, batched: bool = False,
     t0 = time.perf_counter()
     for p in cands:
         ms = float(timer(p))
-        table.append([p.digit_bits, p.tile_keys, p.finish_max, p.offsets, round(ms, 5)])
+        # a candidate that failed its status or output check is listed with
+        # no time and never chosen
+        table.append([p.digit_bits, p.tile_keys, p.finish_max, p.offsets,
+                      round(ms, 5) if math.isfinite(ms) else None])
         if log:
-            log("k=%d tile=%d T=%d offsets=%d: %.4f ms" % (p.digit_bits, p.tile_keys, p.finish_max,
-                                                           p.offsets, ms))
-    best = min(range(len(table)), key=lambda i: (table[i][4], i))
+            log("k=%d tile=%d T=%d offsets=%d: %s" % (p.digit_bits, p.tile_keys, p.finish_max, p.offsets,
+                                                      "%.4f ms" % ms if math.isfinite(ms) else "FAILED"))
+    timed = [i for i in range(len(table)) if table[i][4] is not None]
+    if not timed:
+        raise RuntimeError("autotune: every candidate failed its status or output check")
+    best = min(timed, key=lambda i: (table[i][4], i))
     k, tile, T, off, ms = table[best]
     return {"params": {"digit_bits": k, "tile_keys": tile, "finish_max": T, "offsets": off},
             "ms": ms, "gkeys_s": round(n / (ms * 1e-3) / 1e9, 4) if ms > 0 else None, "n": n,

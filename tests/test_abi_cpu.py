@@ -139,3 +139,19 @@ def test_build_tracks_every_source():
     for f in os.listdir(csrc):
         assert os.path.abspath(os.path.join(csrc, f)) in deps, f
     assert any(p.endswith(os.path.join("include", "binar.h")) for p in deps)
+
+
+def test_plan_segmented_refuses_short_buffers(monkeypatch):
+    """A segmented plan sort whose buffers are shorter than the plan's
+    capacity is refused before the library is called: a segment table that
+    is valid for the capacity would reach past them."""
+    import torch
+    from paper_0811_3448_amd import binar
+    plan = binar.Plan.__new__(binar.Plan)
+    plan._h = ctypes.c_void_p()          # never reaches the library
+    plan.key_bytes, plan.max_keys, plan.max_segments = 4, 1000, 10
+    monkeypatch.setattr(binar, "_check_tensors", lambda k, p: None)
+    keys = torch.zeros(999, dtype=torch.int32)
+    off = torch.zeros(11, dtype=torch.int32)
+    with pytest.raises(ValueError, match="capacity"):
+        plan.sort(keys, torch.zeros(999, dtype=torch.int32), off)

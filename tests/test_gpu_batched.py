@@ -39,7 +39,7 @@ def test_plan_replays_match_oracle_and_eager():
         kbuf[:n] = to_dev(keys)
         pbuf[:n] = torch.arange(n, dtype=torch.int32, device="cuda")
         obuf.copy_(dev_offsets(off))
-        plan.sort(kbuf, pbuf, obuf, n_total=n)
+        plan.sort(kbuf, pbuf, obuf)
         torch.cuda.synchronize()
         assert plan.stats()["status"] == 0
         gk = kbuf[:n].cpu().numpy().view(np.uint32)
@@ -87,16 +87,24 @@ def test_plan_single_array_and_changed_layout():
     plan.close()
 
 
-def test_batched_100k_segments_full_size():
+@pytest.mark.parametrize("params_from", ["library defaults", "autotune cache"])
+def test_batched_100k_segments_full_size(params_from):
     """The batched workload at its full size: 100,000 lognormal segments,
     about 2^27 keys, checked completely by per-segment properties plus the
-    oracle on a sample of segments."""
+    oracle on a sample of segments; once with the library's defaults and
+    once with the parameters the autotune cache holds for this case (the
+    ones the batched benchmark runs)."""
     import torch
     import paper_0811_3448_amd as binar
+    from paper_0811_3448_amd import tune
     keys, off = workloads.batched_u32()
     n, S = int(off[-1]), off.shape[0] - 1
-    print("batched n=%d S=%d" % (n, S), flush=True)
-    plan = binar.Plan(4, n, S, True)
+    params = None
+    if params_from == "autotune cache":
+        params = tune.TuneCache(arch=tune.device_arch()).lookup(4, True, n, True, max_distance=1)
+        assert params is not None, "no batched entry in the autotune cache"
+    print("batched n=%d S=%d params=%s" % (n, S, params), flush=True)
+    plan = binar.Plan(4, n, S, True, params)
     kd, pd = to_dev(keys), torch.arange(n, dtype=torch.int32, device="cuda")
     plan.sort(kd, pd, dev_offsets(off))
     torch.cuda.synchronize()
@@ -107,4 +115,25 @@ def test_batched_100k_segments_full_size():
         a, b = int(off[s]), int(off[s + 1])
         rk, rp = oracle.sort(keys[a:b], np.arange(a, b, dtype=np.uint32))
         assert np.array_equal(gk[a:b], rk) and np.array_equal(gp[a:b], rp), s
+    plan.close()
+
+
+def test_plan_segmented_short_buffers_refused_by_the_library():
+    """Through the C ABI: a segmented plan sort whose n_total (the caller's
+    buffer length) is below the plan's capacity returns BINAR_EINVAL before
+    any device work, and the keys stay as they were."""
+    import ctypes
+    import torch
+    import paper_0811_3448_amd as binar
+    plan = binar.Plan(4, 5000, 4, True)
+    keys = torch.arange(4000, 0, -1, dtype=torch.int32, device="cuda")
+    pay = torch.arange(4000, dtype=torch.int32, device="cuda")
+    off = dev_offsets([0, 1000, 2000, 3000, 4000])
+    before = keys.clone()
+    vp = ctypes.c_void_p
+    rc = binar.lib.binar_plan_sort(plan._h, vp(keys.data_ptr()), vp(pay.data_ptr()), vp(off.data_ptr()), 4, 4000,
+                                   None)
+    assert rc == binar.BINAR_EINVAL
+    torch.cuda.synchronize()
+    assert torch.equal(keys, before)
     plan.close()

@@ -425,3 +425,171 @@ def test_strings_fixed_length_match_lexsort():
     a = rng.integers(0, 3, (3000, 7)).astype(np.uint8)
     data, offs = strings.pack([bytes(r) for r in a])
     assert np.array_equal(strings.stable_order(data, offs), np.lexsort(a.T[::-1]))
+
+
+# ------------------------------------- pins of the helpers the GPU tests use
+# definition.stable_rank_u gives the expected positions in the full-size
+# parity tests; orders.sort_segmented the expected result of segmented signed
+# and float sorts; strings.sort the direction in which the payload follows the
+# strings.  Each is checked against code it does not share, and a planted
+# mistake (written here, on the CPU) must fail the same check.
+
+def _ranks_from_oracle(keys):
+    """Output position of every input element under the C oracle: the
+    inverse of the permutation it carries in an index payload."""
+    _, p = oracle.sort(keys, iota(keys.shape[0]))
+    inv = np.empty(keys.shape[0], dtype=np.int64)
+    inv[p.astype(np.int64)] = np.arange(keys.shape[0])
+    return inv
+
+
+def _rank_le_mistake(keys, j):
+    """stable_rank_u with `<=` for `<` (a plausible slip)."""
+    kj = keys[j]
+    return int(np.count_nonzero(keys <= kj)) + int(np.count_nonzero(keys[:j] == kj))
+
+
+def _rank_tie_mistake(keys, j):
+    """stable_rank_u counting equal keys after j instead of before it."""
+    kj = keys[j]
+    return int(np.count_nonzero(keys < kj)) + int(np.count_nonzero(keys[j + 1:] == kj))
+
+
+@pytest.mark.parametrize("dtype,seed", [(np.uint32, 71), (np.uint64, 72)])
+def test_stable_rank_matches_oracle_positions(dtype, seed):
+    """Heavy ties (eight values) plus the extremes of the key range; every
+    element, including the first and the last index."""
+    rng = np.random.default_rng(seed)
+    top = np.iinfo(dtype).max
+    pool = np.array([0, 1, 7, top // 2, top // 2 + 1, top - 1, top, 12345], dtype=dtype)
+    keys = pool[rng.integers(0, pool.shape[0], 3000)]
+    keys[0], keys[-1] = pool[3], pool[3]           # first and last tie with each other
+    ranks = _ranks_from_oracle(keys)
+    got = [definition.stable_rank_u(keys, j) for j in range(keys.shape[0])]
+    assert got == ranks.tolist()
+    assert got[0] < got[-1]                        # the tie keeps input order
+
+
+def test_stable_rank_brute_force_small():
+    """Against the brute-force stable permutation on tiny inputs."""
+    rng = np.random.default_rng(73)
+    for _ in range(30):
+        n = int(rng.integers(1, 8))
+        keys = rng.integers(0, 3, n).astype(np.uint32)
+        perm = brute_force_stable(keys)
+        want = [perm.index(j) for j in range(n)]
+        assert [definition.stable_rank_u(keys, j) for j in range(n)] == want
+
+
+def test_stable_rank_planted_mistakes_fail():
+    keys = np.array([5, 3, 5, 5, 0, 3, 9, 5], dtype=np.uint32)
+    ranks = _ranks_from_oracle(keys).tolist()
+    assert [definition.stable_rank_u(keys, j) for j in range(8)] == ranks
+    assert [_rank_le_mistake(keys, j) for j in range(8)] != ranks
+    assert [_rank_tie_mistake(keys, j) for j in range(8)] != ranks
+
+
+def _segments_with_edges(n_seg, seed, total_hint):
+    """Offsets with empty and one-key segments among random lengths."""
+    rng = np.random.default_rng(seed)
+    lens = rng.integers(0, 2 * total_hint // n_seg, n_seg)
+    lens[:6] = [0, 1, 0, 2, 1, 0]
+    lens[-1] = 0
+    off = np.zeros(n_seg + 1, dtype=np.int64)
+    off[1:] = np.cumsum(lens)
+    return off
+
+
+def _per_segment_numpy(values, off):
+    """Per segment, numpy's stable argsort of the values, as global indices."""
+    p = np.arange(values.shape[0], dtype=np.int64)
+    for s in range(off.shape[0] - 1):
+        a, b = int(off[s]), int(off[s + 1])
+        p[a:b] = a + np.argsort(values[a:b], kind="stable")
+    return p
+
+
+def test_orders_segmented_unsigned_matches_c_oracle():
+    from oracle import orders
+    off = _segments_with_edges(60, 74, 3000)
+    n = int(off[-1])
+    keys = workloads.u32_uniform(n, 75) >> np.uint32(24)         # ties
+    pay = (np.arange(n, dtype=np.uint32) * np.uint32(7919)) ^ np.uint32(0xABC)
+    ok, op = orders.sort_segmented(keys, off, pay, orders.UNSIGNED)
+    rk, rp = oracle.sort_segmented(keys, off, pay)
+    assert np.array_equal(ok, rk) and np.array_equal(op, rp)
+
+
+@pytest.mark.parametrize("width", [32, 64])
+def test_orders_segmented_signed_float_match_numpy(width):
+    from oracle import orders
+    off = _segments_with_edges(80, 76 + width, 4000)
+    n = int(off[-1])
+    rng = np.random.default_rng(78 + width)
+    it, ut, ft = (np.int32, np.uint32, np.float32) if width == 32 else (np.int64, np.uint64, np.float64)
+    pay = rng.permutation(n).astype(np.uint32)                  # not the identity
+    # signed: ties, both extremes, values of both signs
+    v = rng.integers(-50, 50, n).astype(it)
+    v[::97] = np.iinfo(it).min
+    v[1::89] = np.iinfo(it).max
+    ok, op = orders.sort_segmented(v.view(ut), off, pay, orders.SIGNED)
+    p = _per_segment_numpy(v, off)
+    assert np.array_equal(op, pay[p]) and np.array_equal(ok.view(it), v[p])
+    # float, numerically ordered by numpy (zeros and NaNs are pinned apart)
+    f = (rng.standard_normal(n) * 10.0 ** rng.integers(-5, 5, n)).astype(ft)
+    f[::53] = f[0]
+    f[f == 0] = 1
+    ok, op = orders.sort_segmented(f.view(ut), off, pay, orders.FLOAT)
+    p = _per_segment_numpy(f, off)
+    assert np.array_equal(op, pay[p]) and np.array_equal(ok.view(ft), f[p])
+
+
+def test_orders_segmented_bounds_mistake_fails():
+    """Segments that leak into their neighbours (one key too far) must fail
+    the same per-segment check."""
+    from oracle import orders
+    off = np.array([0, 5, 5, 6, 12], dtype=np.int64)
+    v = np.array([9, 1, 8, 2, 7, 3, 6, 0, 5, 4, 4, 1], dtype=np.int32)
+    pay = np.arange(12, dtype=np.uint32)
+    ok, op = orders.sort_segmented(v.view(np.uint32), off, pay, orders.SIGNED)
+    assert np.array_equal(op, pay[_per_segment_numpy(v, off)])
+    leaky = off.copy()
+    leaky[1] += 1
+    _, bad = orders.sort_segmented(v.view(np.uint32), leaky, pay, orders.SIGNED)
+    assert not np.array_equal(bad, pay[_per_segment_numpy(v, off)])
+
+
+def _lexsort_strings(data, offs):
+    """Stable order of variable-length strings by numpy's lexsort: zero-padded
+    byte columns (byte 0 primary), then the length (a proper prefix first,
+    also before its extensions by zero bytes), then the input index."""
+    o = np.asarray(offs, dtype=np.int64)
+    n = o.shape[0] - 1
+    lens = o[1:] - o[:-1]
+    width = int(lens.max()) if n else 0
+    cols = np.zeros((n, max(width, 1)), dtype=np.uint8)
+    for i in range(n):
+        cols[i, :lens[i]] = data[o[i]:o[i + 1]]
+    keys = [np.arange(n), lens] + [cols[:, c] for c in range(cols.shape[1] - 1, -1, -1)]
+    return np.lexsort(keys)
+
+
+def test_strings_sort_payload_direction():
+    """strings.sort returns payload[p] (output i carries the payload of the
+    i-th smallest string), checked with a payload that is not the identity;
+    the inverse permutation (a plausible slip) must fail."""
+    from oracle import strings
+    rng = np.random.default_rng(79)
+    alpha = np.frombuffer(b"ab\x00", dtype=np.uint8)
+    s = [bytes(alpha[rng.integers(0, 3, int(rng.integers(0, 6)))]) for _ in range(400)]
+    data, offs = strings.pack(s)
+    pay = (rng.permutation(400).astype(np.uint32) * np.uint32(3)) + np.uint32(11)
+    order = _lexsort_strings(data, offs)
+    got = strings.sort(data, offs, pay)
+    assert np.array_equal(got, pay[order])
+    inv = np.empty_like(order)
+    inv[order] = np.arange(order.shape[0])
+    assert not np.array_equal(pay[inv], pay[order])
+    # and the strings the payload points at are in order
+    srt = [s[int(i)] for i in order]
+    assert all(srt[i] <= srt[i + 1] for i in range(len(srt) - 1))

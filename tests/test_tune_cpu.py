@@ -108,3 +108,19 @@ def test_lognormal_offsets(n):
     assert (d >= 1).all() and d.max() <= 1 << 20
     if n >= 1 << 20:
         assert 700 < np.median(d) < 1400
+
+
+def test_autotune_never_picks_a_failed_candidate():
+    """A candidate whose status or output check failed (the timer reports
+    inf) is listed without a time and never chosen, however fast it looked;
+    if every candidate failed, tuning fails."""
+    import math
+    cands = tune.candidates(4, True)
+    cost = {id(p): 10.0 + i for i, p in enumerate(cands)}
+    cost[id(cands[3])] = math.inf
+    cost[id(cands[9])] = 2.0
+    e = tune.autotune(4, True, 1 << 20, timer=lambda p: cost[id(p)], cands=cands)
+    assert e["params"]["digit_bits"] == cands[9].digit_bits and e["ms"] == 2.0
+    assert e["table"][3][4] is None
+    with pytest.raises(RuntimeError):
+        tune.autotune(4, True, 1 << 20, timer=lambda p: math.inf, cands=cands[:4])
