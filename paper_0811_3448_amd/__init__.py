@@ -9,6 +9,11 @@ C ABI.  The binding only marshals arguments: torch tensors supply device
 memory and streams, every step of the sort runs in the library's kernels.
 """
 from .binar import (  # noqa: F401
+    BINAR_EDEVICE,
+    BINAR_EINVAL,
+    BINAR_ENOMEM,
+    BINAR_ERANGE,
+    BINAR_OK,
     KEY_FLOAT,
     KEY_SIGNED,
     KEY_UNSIGNED,
