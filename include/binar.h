@@ -265,6 +265,26 @@ int binar_sort_inplace(void *keys, uint32_t key_bytes, uint64_t n, uint32_t *pay
                        void *stream, void *workspace, size_t workspace_bytes);
 size_t binar_inplace_workspace_bytes(uint32_t key_bytes, uint64_t n, int has_payload, const binar_params *params);
 
+/* Allocation-free sort, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The same operation and result as binar_sort_async on one
+ * array (keys and payload are caller-owned device buffers, payload may be
+ * NULL), enqueued on `stream`, but the scratch is a fixed array of
+ * BINAR_STATIC_SCRATCH_BYTES inside the library, one per device, set up on
+ * the first call on that device and held until the process ends.  The call
+ * allocates nothing: no hipMalloc, no hipFree, no pool growth, no timing
+ * events.  n is bounded by what fits: a call with
+ * binar_workspace_bytes(key_bytes, n, payload != NULL, 1, NULL) above
+ * BINAR_STATIC_SCRATCH_BYTES returns BINAR_ENOMEM before any device work
+ * (about 3.9M 4-byte keys with payload, 3.1M 8-byte keys with payload,
+ * 2.2M 16-byte keys with payload).  Every call on one device shares that
+ * device's array, which keeps the last call's contents (each call clears
+ * what it needs itself): calls that overlap in time on one device race,
+ * whatever their streams.  binar_stats_read(NULL, stream, ...) reads the
+ * counters of the last such call.  Errors as for binar_sort_async. */
+#define BINAR_STATIC_SCRATCH_BYTES (64u << 20)
+int binar_sort_static(void *keys, uint32_t key_bytes, uint64_t n, uint32_t *payload, void *stream);
+
 /* Static description of a status code. */
 const char *binar_strerror(int status);
 

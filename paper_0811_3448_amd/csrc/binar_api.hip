@@ -157,7 +157,8 @@ struct Pool {
 };
 std::mutex g_pool_mu;
 std::vector<Pool> g_pools;
-std::vector<const void *> g_last_ws;  // per device: workspace of the last call
+constexpr int MAX_WS_DEVICES = 64;
+const void *g_last_ws[MAX_WS_DEVICES];  // per device: workspace of the last call
 
 int pool_get(int dev, size_t bytes, void **out) {
     std::lock_guard<std::mutex> lk(g_pool_mu);
@@ -184,8 +185,7 @@ int pool_get(int dev, size_t bytes, void **out) {
 
 void note_ws(int dev, const void *ws) {
     std::lock_guard<std::mutex> lk(g_pool_mu);
-    if ((int)g_last_ws.size() <= dev) g_last_ws.resize(dev + 1, nullptr);
-    g_last_ws[dev] = ws;
+    if (dev >= 0 && dev < MAX_WS_DEVICES) g_last_ws[dev] = ws;
 }
 
 Work make_work(const Layout &L, const Resolved &r, char *ws, void *keys, uint32_t *pay, uint32_t n_total) {
@@ -434,7 +434,7 @@ int sort_strings(const uint8_t *bytes, uint64_t nbytes, const uint32_t *offs, ui
 
 const void *last_ws(int dev) {
     std::lock_guard<std::mutex> lk(g_pool_mu);
-    return (dev < (int)g_last_ws.size()) ? g_last_ws[dev] : nullptr;
+    return (dev >= 0 && dev < MAX_WS_DEVICES) ? g_last_ws[dev] : nullptr;
 }
 
 }  // namespace
