@@ -285,6 +285,21 @@ size_t binar_inplace_workspace_bytes(uint32_t key_bytes, uint64_t n, int has_pay
 #define BINAR_STATIC_SCRATCH_BYTES (64u << 20)
 int binar_sort_static(void *keys, uint32_t key_bytes, uint64_t n, uint32_t *payload, void *stream);
 
+/* Measurement helpers: the rate a plain streaming pass over device memory
+ * reaches, to set the sort's passes against (a pass reads and writes its
+ * bytes once, a digit count reads them once).  binar_stream_copy copies
+ * `bytes` from src to dst (device, 16-byte aligned, bytes a multiple of 16,
+ * not overlapping) with streaming stores; binar_stream_read reads src and
+ * stores one XOR of its words per block to out (device, at least
+ * blocks_per_cu x compute units words).  Both run a persistent grid of
+ * blocks_per_cu (1..32) 256-thread blocks per compute unit with `unroll`
+ * (2, 4 or 8) 16-byte vectors in flight per thread; BINAR_EINVAL for other
+ * arguments.  Asynchronous on stream. */
+int binar_stream_copy(void *dst, const void *src, size_t bytes, uint32_t blocks_per_cu, uint32_t unroll,
+                      void *stream);
+int binar_stream_read(const void *src, size_t bytes, uint32_t *out, uint32_t blocks_per_cu, uint32_t unroll,
+                      void *stream);
+
 /* Static description of a status code. */
 const char *binar_strerror(int status);
 

@@ -50,6 +50,8 @@ def _load():
     L.binar_sort.argtypes = [vp, u32, u64, vp]
     L.binar_sort_async.argtypes = [vp, u32, u64, vp, vp, vp, sz]
     L.binar_sort_static.argtypes = [vp, u32, u64, vp, vp]
+    L.binar_stream_copy.argtypes = [vp, vp, sz, u32, u32, vp]
+    L.binar_stream_read.argtypes = [vp, sz, vp, u32, u32, vp]
     L.binar_sort_segmented.argtypes = [vp, u32, vp, u32, u64, vp, vp, vp, sz]
     L.binar_sort_ex.argtypes = [vp, u32, u64, vp, vp, u32, P, vp, vp, sz]
     L.binar_workspace_bytes.argtypes = [u32, u64, i32, u32, P]
@@ -79,7 +81,8 @@ def _load():
     L.binar_inplace_workspace_bytes.restype = sz
     L.binar_last_error.argtypes = []
     L.binar_last_error.restype = ctypes.c_char_p
-    for f in ("binar_sort", "binar_sort_async", "binar_sort_static", "binar_sort_segmented", "binar_sort_ex",
+    for f in ("binar_sort", "binar_sort_async", "binar_sort_static", "binar_stream_copy", "binar_stream_read",
+              "binar_sort_segmented", "binar_sort_ex",
               "binar_stats_read", "binar_get_default_params", "binar_set_default_params", "binar_resolve_params",
               "binar_profile_enable", "binar_profile_read", "binar_plan_create", "binar_plan_sort",
               "binar_plan_stats", "binar_plan_graphs"):

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbinar.so")
 SOURCES = [os.path.join(CSRC, f) for f in
-           ["binar_api.hip", "binar_static.hip"] + ["binar_launch_%d%s.hip" % (kb, t) for kb in (4, 8, 16) for t in "pk"]]
+           ["binar_api.hip", "binar_static.hip", "binar_stream.hip"] + ["binar_launch_%d%s.hip" % (kb, t) for kb in (4, 8, 16) for t in "pk"]]
 HEADERS = [os.path.join(CSRC, f) for f in
            ("binar_host.h", "binar_kernels.h", "binar_keys.h", "binar_inplace.h", "binar_strings.h")]
 DEPS = SOURCES + HEADERS + [os.path.join(ROOT, "include", "binar.h")]

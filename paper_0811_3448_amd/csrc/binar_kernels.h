@@ -1405,20 +1405,58 @@ struct FinishLds {
     uint32_t long_run;
 };
 
+// Keys [wb, we) of a sub-array of len keys held by wave wv of a BT-thread
+// block: the keys are spread evenly over the waves (it = ceil(len / (waves
+// * 64)) steps of 64 consecutive keys each, at most ITEMS), so (wave, step,
+// lane) order is the input order.  Lanes past we hold nothing in any step.
+template <int BT, int ITEMS>
+__device__ __forceinline__ void wave_share(uint32_t len, int wv, uint32_t &wb, uint32_t &we) {
+    constexpr uint32_t NW = BT / WAVE;
+    uint32_t it = (len + NW * WAVE - 1) / (NW * WAVE);
+    it = it < (uint32_t)ITEMS ? it : (uint32_t)ITEMS;
+    wb = uni((uint32_t)wv * it * WAVE);
+    we = uni(min(len, wb + it * WAVE));
+}
+
+// Per digit: the staged offset of each wave's keys (exclusive scan over the
+// digits of the block's counts, then over the waves), left in S.wh in place
+// of the wave counts.  Every thread calls it (it holds barriers).
+template <int BT, class L>
+__device__ __forceinline__ void fin_offsets(L &S) {
+    constexpr int R = 256;
+    constexpr int NW = BT / WAVE;
+    __syncthreads();
+    uint32_t tcnt = 0;
+    if (threadIdx.x < R) {
+#pragma unroll
+        for (int q = 0; q < NW; ++q) tcnt += S.wh[q][threadIdx.x];
+    }
+    uint32_t tot;
+    uint32_t acc = block_excl_scan<BT>(tcnt, S.tmp, &tot);  // every thread: it holds barriers
+    if (threadIdx.x < R) {
+#pragma unroll
+        for (int q = 0; q < NW; ++q) {
+            const uint32_t x = S.wh[q][threadIdx.x];
+            S.wh[q][threadIdx.x] = acc;
+            acc += x;
+        }
+    }
+    __syncthreads();
+}
+
 // Stable LDS passes over the varying bits of the segment in S with bit
 // index in [bitpos, end] (MSB-first indices), least significant window of up
 // to 8 bits first; constant windows are skipped.  The order lives in S
-// between passes.
+// between passes.  Each wave ranks its share [ebase - lane, we)
+// (wave_share).
 template <int KB, int BT, int ITEMS, bool PAY>
 __device__ __forceinline__ void lds_passes(FinishLds<KB, BT, ITEMS, PAY> &S, Canon diff, int bitpos, int end,
-                                           uint32_t len) {
+                                           uint32_t ebase, uint32_t we) {
     using KT = KeyT<KB>;
     using V = typename KT::V;
     constexpr int KL = 8;
     constexpr int R = 1 << KL;
-    constexpr int NW = BT / WAVE;
     const int wv = threadIdx.x / WAVE, lane = lane_id();
-    const uint32_t ebase = (uint32_t)wv * ITEMS * WAVE + (uint32_t)lane;
     int hib = last_set_below(diff, bitpos, end + 1);
     while (hib >= bitpos) {
         const int lo = max(bitpos, hib - KL + 1);
@@ -1428,37 +1466,21 @@ __device__ __forceinline__ void lds_passes(FinishLds<KB, BT, ITEMS, PAY> &S, Can
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
             const uint32_t e = ebase + j * WAVE;
-            key[j] = (e < len) ? S.keys[e] : KT::zero();
+            key[j] = (e < we) ? S.keys[e] : KT::zero();
             dg[j] = KT::digit(key[j], lo, wbits);
         }
-        wave_rank<R, RANK_GROUP, ITEMS, false>(dg, ebase, len, &S.tbl[wv][0], &S.wh[wv][0], rnk);
+        wave_rank<R, RANK_GROUP, ITEMS, false>(dg, ebase, we, &S.tbl[wv][0], &S.wh[wv][0], rnk);
         uint32_t pay[ITEMS];
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
             const uint32_t e = ebase + j * WAVE;
-            if (PAY) pay[j] = (e < len) ? S.pay[e] : 0u;
+            if (PAY) pay[j] = (e < we) ? S.pay[e] : 0u;
         }
-        __syncthreads();
-        uint32_t tcnt = 0;
-        if (threadIdx.x < R) {
-#pragma unroll
-            for (int q = 0; q < NW; ++q) tcnt += S.wh[q][threadIdx.x];
-        }
-        uint32_t tot;
-        uint32_t acc = block_excl_scan<BT>(tcnt, S.tmp, &tot);  // every thread: it holds barriers
-        if (threadIdx.x < R) {
-#pragma unroll
-            for (int q = 0; q < NW; ++q) {
-                const uint32_t x = S.wh[q][threadIdx.x];
-                S.wh[q][threadIdx.x] = acc;
-                acc += x;
-            }
-        }
-        __syncthreads();
+        fin_offsets<BT>(S);
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
             const uint32_t e = ebase + j * WAVE;
-            if (e < len) {
+            if (e < we) {
                 const uint32_t pos = S.wh[wv][dg[j]] + rnk[j];
                 S.keys[pos] = key[j];
                 if (PAY) S.pay[pos] = pay[j];
@@ -1469,6 +1491,115 @@ __device__ __forceinline__ void lds_passes(FinishLds<KB, BT, ITEMS, PAY> &S, Can
         // the next barrier
         for (int i = lane; i < R; i += WAVE) S.wh[wv][i] = 0u;
         hib = last_set_below(diff, bitpos, lo);
+    }
+}
+
+// The 16 bits [s, s + 16) (MSB-first) of a 4- or 8-byte key, and a key
+// rebuilt from them over the bits `base` has outside that field.
+template <int KB>
+__device__ __forceinline__ uint32_t field16(typename KeyT<KB>::V v, int s) {
+    return (uint32_t)(v >> (8 * KB - 16 - s)) & 0xFFFFu;
+}
+
+template <int KB>
+__device__ __forceinline__ typename KeyT<KB>::V unfield16(typename KeyT<KB>::V base, uint32_t f, int s) {
+    using V = typename KeyT<KB>::V;
+    const int sh = 8 * KB - 16 - s;
+    return (base & ~((V)0xFFFFu << sh)) | ((V)f << sh);
+}
+
+// The same passes for a sub-array whose varying bits all lie in the 16 bits
+// [s, s + 16) (MSB-first): each key travels as one 32-bit word, (those 16
+// bits << 16) | its index in the sub-array, so that a pass moves 4 bytes per
+// key whatever the key width, and the payload stays where it was loaded.
+// Windows of up to 8 bits from lb down to fb.  On return the words in sorted
+// order are in S.keys, read as 32-bit words (word i = the i-th key).
+template <int KB, int BT, int ITEMS, bool PAY>
+__device__ __forceinline__ void packed_passes(FinishLds<KB, BT, ITEMS, PAY> &S, Canon diff, int fb, int lb, int s,
+                                              uint32_t ebase, uint32_t we) {
+    typedef uint32_t __attribute__((may_alias)) word_t;
+    word_t *pk = reinterpret_cast<word_t *>(&S.keys[0]);
+    constexpr int R = 256;
+    const int wv = threadIdx.x / WAVE, lane = lane_id();
+    uint32_t pw[ITEMS];
+    // the words, from the keys in input order (every read comes before the
+    // barriers of the first window, every write after them)
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const uint32_t e = ebase + j * WAVE;
+        pw[j] = (e < we) ? (field16<KB>(S.keys[e], s) << 16) | e : 0u;
+    }
+    int hib = lb;
+    bool first = true;
+    while (hib >= fb) {
+        const int lo = max(fb, hib - 7);
+        const uint32_t mask = (1u << (hib - lo + 1)) - 1u;
+        const int sh = 31 - (hib - s);  // the window's least significant bit in a word
+        uint32_t dg[ITEMS], rnk[ITEMS];
+        if (!first) {
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) {
+                const uint32_t e = ebase + j * WAVE;
+                pw[j] = (e < we) ? pk[e] : 0u;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) dg[j] = (pw[j] >> sh) & mask;
+        wave_rank<R, RANK_GROUP, ITEMS, false>(dg, ebase, we, &S.tbl[wv][0], &S.wh[wv][0], rnk);
+        fin_offsets<BT>(S);
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const uint32_t e = ebase + j * WAVE;
+            if (e < we) pk[S.wh[wv][dg[j]] + rnk[j]] = pw[j];
+        }
+        __syncthreads();
+        for (int i = lane; i < R; i += WAVE) S.wh[wv][i] = 0u;
+        hib = last_set_below(diff, fb, lo);
+        first = false;
+    }
+}
+
+// The packed sort's result from LDS to [g0, g1) of A: word i of pk is the
+// i-th key's 16-bit field and its index in the sub-array, whose payload is
+// pay[index]; keys are rebuilt over `base` (the bits every key shares).
+// Whole 16-byte vectors for the aligned body of each buffer.
+template <int KB, int BT, bool PAY>
+__device__ __forceinline__ void fin_store_packed(const Work &w, size_t g0, size_t g1, const uint32_t *pk,
+                                                 const uint32_t *pay, typename KeyT<KB>::V base, int s) {
+    using KT = KeyT<KB>;
+    constexpr int VN = Vec<KB>::N;
+    void *dst = w.keys[0];
+    size_t b0, b1;
+    aligned_body<VN, KB>(dst, g0, g1, b0, b1);
+    for (size_t i = g0 + threadIdx.x; i < b0; i += BT)
+        KT::store(dst, i, raw_key<KB>(unfield16<KB>(base, pk[i - g0] >> 16, s), w.kind));
+    for (size_t i = b1 + threadIdx.x; i < g1; i += BT)
+        KT::store(dst, i, raw_key<KB>(unfield16<KB>(base, pk[i - g0] >> 16, s), w.kind));
+    for (size_t x = b0 + (size_t)threadIdx.x * VN; x < b1; x += (size_t)BT * VN) {
+        const uint32_t *q = pk + (x - g0);
+        if constexpr (KB == 4) {
+            *reinterpret_cast<uint4 *>(reinterpret_cast<uint32_t *>(dst) + x) =
+                make_uint4(raw_key<KB>(unfield16<KB>(base, q[0] >> 16, s), w.kind),
+                           raw_key<KB>(unfield16<KB>(base, q[1] >> 16, s), w.kind),
+                           raw_key<KB>(unfield16<KB>(base, q[2] >> 16, s), w.kind),
+                           raw_key<KB>(unfield16<KB>(base, q[3] >> 16, s), w.kind));
+        } else {
+            ulonglong2 r;
+            r.x = raw_key<KB>(unfield16<KB>(base, q[0] >> 16, s), w.kind);
+            r.y = raw_key<KB>(unfield16<KB>(base, q[1] >> 16, s), w.kind);
+            *reinterpret_cast<ulonglong2 *>(reinterpret_cast<uint64_t *>(dst) + x) = r;
+        }
+    }
+    if constexpr (PAY) {
+        uint32_t *pdst = w.pay[0];
+        aligned_body<4, 4>(pdst, g0, g1, b0, b1);
+        for (size_t i = g0 + threadIdx.x; i < b0; i += BT) pdst[i] = pay[pk[i - g0] & 0xFFFFu];
+        for (size_t i = b1 + threadIdx.x; i < g1; i += BT) pdst[i] = pay[pk[i - g0] & 0xFFFFu];
+        for (size_t x = b0 + (size_t)threadIdx.x * 4; x < b1; x += (size_t)BT * 4) {
+            const uint32_t *q = pk + (x - g0);
+            *reinterpret_cast<uint4 *>(pdst + x) = make_uint4(pay[q[0] & 0xFFFFu], pay[q[1] & 0xFFFFu],
+                                                              pay[q[2] & 0xFFFFu], pay[q[3] & 0xFFFFu]);
+        }
     }
 }
 
@@ -1676,8 +1807,9 @@ void k_finish(Work w, int cls) {
         }
         __syncthreads();
         Canon diff{0ull, 0ull};
+        unsigned long long ah = ~0ull;  // bits every key has (the high word)
         {
-            unsigned long long ah = ~0ull, al = ~0ull, oh = 0ull, ol = 0ull;
+            unsigned long long al = ~0ull, oh = 0ull, ol = 0ull;
 #pragma unroll
             for (int q = 0; q < NW; ++q) {
                 ah &= S.ao[q][0];
@@ -1694,16 +1826,34 @@ void k_finish(Work w, int cls) {
             __syncthreads();
             continue;
         }
+        uint32_t wb, we;
+        wave_share<BT, ITEMS>(len, wv, wb, we);
+        const uint32_t ebase = wb + (uint32_t)lane;
+        const int fb = first_set_from(diff, bitpos, NB);
+        if constexpr (KB != 16) {
+            // every varying bit of the keys (those after the sorted ones
+            // included) inside one 16-bit field: sort one word per key
+            const int s = min(fb, 8 * KB - 16);
+            const uint64_t fmask = (0xFFFFull << 48) >> s;  // the field in the left-aligned word
+            if (lb >= bitpos && lb - s <= 15 && ((diff.hi & ~fmask) | diff.lo) == 0ull) {
+                packed_passes<KB, BT, ITEMS, PAY>(S, diff, fb, lb, s, ebase, we);
+                typedef uint32_t __attribute__((may_alias)) word_t;
+                const V base = (KB == 4) ? (V)(ah >> 32) : (V)ah;
+                fin_store_packed<KB, BT, PAY>(w, fe.begin, (size_t)fe.begin + len,
+                                              reinterpret_cast<const word_t *>(&S.keys[0]), S.pay, base, s);
+                __syncthreads();
+                continue;
+            }
+        }
         if (lb >= bitpos) {
             // sort by the two leading 8-bit windows that start at varying bits;
             // keys still tied on them are ordered by fix_runs, or, if a tied
             // run is long, by passes over every varying bit
-            const int fb = first_set_from(diff, bitpos, NB);
             const int f2 = first_set_from(diff, min(fb + 8, NB), NB);
             const int pe = (f2 >= NB) ? lb : min(lb, f2 + 7);
-            lds_passes<KB, BT, ITEMS, PAY>(S, diff, bitpos, pe, len);
+            lds_passes<KB, BT, ITEMS, PAY>(S, diff, bitpos, pe, ebase, we);
             if (pe < lb && fix_runs<KB, BT, ITEMS, PAY>(S, pe, len, NB))
-                lds_passes<KB, BT, ITEMS, PAY>(S, diff, bitpos, lb, len);
+                lds_passes<KB, BT, ITEMS, PAY>(S, diff, bitpos, lb, ebase, we);
         }
         fin_store_keys<KB, BT>(w.keys[0], fe.begin, (size_t)fe.begin + len, S.keys, w.kind);
         if constexpr (PAY) fin_store_pay<BT>(w.pay[0], fe.begin, (size_t)fe.begin + len, S.pay);
