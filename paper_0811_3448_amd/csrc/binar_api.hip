@@ -102,7 +102,7 @@ int resolve(uint32_t kb, bool pay, const binar_params *p, Resolved *r) {
     return resolve_over(kb, pay, d, p, r);
 }
 
-Layout make_layout(const Resolved &r, uint64_t n) {
+Layout make_layout(const Resolved &r, uint64_t n, bool single = true) {
     Layout L{};
     const uint32_t R = 1u << r.k;
     L.max_big = (uint32_t)(n / (r.T + 1ull) + 1ull);
@@ -146,6 +146,14 @@ Layout make_layout(const Resolved &r, uint64_t n) {
     L.nstate = r.inplace ? (uint32_t)(n / 32 + 2) : 0u;
     L.segmap = take((size_t)L.nmap * sizeof(uint4));
     L.state = take((size_t)L.nstate * 4);
+    // pass 0's digit-pair counts (one array of at least PAIR_MIN_KEYS keys):
+    // a row per digit-count block (at most two per compute unit) and the sum
+    L.pair_rows = (single && !r.inplace && !r.lookback && r.k >= 4 && n >= PAIR_MIN_KEYS)
+                      ? (uint32_t)(2 * cu_count())
+                      : 0u;
+    const size_t pair_words = ((size_t)R * R) / 2;
+    L.pair_part = take((size_t)L.pair_rows * pair_words * 4);
+    L.pair_sum = take(L.pair_rows ? (size_t)R * R * 4 : 0);
     L.total = off;
     return L;
 }
@@ -217,6 +225,9 @@ Work make_work(const Layout &L, const Resolved &r, char *ws, void *keys, uint32_
     w.kind = r.kind;
     w.inplace = r.inplace ? 1u : 0u;
     w.n_total = n_total;
+    w.pair_rows = L.pair_rows;
+    w.pair_part = reinterpret_cast<uint32_t *>(ws + L.pair_part);
+    w.pair_sum = reinterpret_cast<uint32_t *>(ws + L.pair_sum);
     w.keys[0] = keys;
     w.keys[1] = r.inplace ? nullptr : ws + L.keys_b;
     w.pay[0] = pay;
@@ -254,7 +265,7 @@ int run(void *keys, uint32_t kb, uint64_t n, uint32_t *payload, const uint32_t *
     Resolved r;
     int rc = resolve(kb, payload != nullptr, params, &r);
     if (rc) return rc;
-    const Layout L = make_layout(r, n);
+    const Layout L = make_layout(r, n, seg_off == nullptr);
     int dev = 0;
     BINAR_HIP_TRY(hipGetDevice(&dev));
     if (ws) {
@@ -358,7 +369,7 @@ StrLayout str_layout(uint64_t n) {
     S.keys = take(16 * n);
     Resolved r;
     (void)resolve(16, true, nullptr, &r);
-    S.inner_bytes = make_layout(r, n < 2 ? 2 : n).total;
+    S.inner_bytes = make_layout(r, n < 2 ? 2 : n, false).total;  // the inner sorts are segmented
     S.inner = take(S.inner_bytes);
     S.total = off;
     return S;
@@ -492,7 +503,7 @@ int binar_plan_create(binar_plan **out, uint32_t key_bytes, uint64_t max_keys, u
     }
     p->max_keys = max_keys < 2 ? 2 : max_keys;
     p->max_segments = max_segments;
-    p->L = make_layout(p->r, p->max_keys);
+    p->L = make_layout(p->r, p->max_keys, max_segments == 1u);
     if (const hipError_t e = hipGetDevice(&p->dev)) {
         delete p;
         return hip_fail("hipGetDevice", e);
@@ -616,11 +627,10 @@ int binar_sort(void *keys, uint32_t key_bytes, uint64_t n, uint32_t *payload) {
 
 size_t binar_workspace_bytes(uint32_t key_bytes, uint64_t n, int has_payload, uint32_t num_segments,
                              const binar_params *params) {
-    (void)num_segments;
     if (!valid_kb(key_bytes) || n > BINAR_MAX_KEYS) return 0;
     Resolved r;
     if (resolve(key_bytes, has_payload != 0, params, &r)) return 0;
-    return make_layout(r, n).total;
+    return make_layout(r, n, num_segments <= 1u).total;
 }
 
 int binar_stats_read(const void *workspace, void *stream, binar_stats *out) {

@@ -97,10 +97,16 @@ struct Resolved {
 
 struct Layout {
     size_t ctl, list[2], counts[2], bases[2], andor[2], desc[2], pcnt, status, fin[NCLASS], fin_small, cpy, keys_b,
-        pay_b, segmap, state, total;
+        pay_b, segmap, state, pair_part, pair_sum, total;
     uint32_t nmap, nstate;  // in place: segment-map entries and state words
     uint32_t max_big, max_tiles, max_fin[NCLASS], fin_cap[NCLASS], max_small, max_cpy;
+    uint32_t pair_rows;     // rows of pass 0's pair counts (0: the next pass counts its own digits)
 };
+
+// One array of at least this many keys counts digit pairs in its first
+// pass, so that the second reads no key for its counts (below it the pair
+// rows cost more than the read they save).
+constexpr uint64_t PAIR_MIN_KEYS = 1ull << 26;
 
 // Blocks each kernel keeps resident per CU (cached per kernel).
 struct OccCache {
@@ -239,15 +245,32 @@ int enqueue(Work w, const Layout &L, const uint32_t *seg_off, uint32_t nseg, uin
     const uint32_t pg = std::max(1u, std::min(L.max_big, 1024u));
     constexpr uint32_t NG = (R < 32) ? 1u : (uint32_t)R / 32u;
     const uint32_t qg = std::max(1u, std::min(L.max_big * NG, 2048u));
+    // digit pairs in the first pass: one array (no segment table), chunk
+    // offsets, a pair row for every digit-count block, two passes or more
+    const bool pairs = !LB && K >= 4 && seg_off == nullptr && nseg == 1u && L.pair_rows != 0u && hg <= L.pair_rows &&
+                       passes >= 2;
+    if (!pairs) w.pair_rows = 0u;
     for (int j = 0; j < passes; ++j) {
         const int Lc = j & 1;
         {
             Timed tm(st, "k_hist", j);
-            hipLaunchKernelGGL((k_hist<KB, K, LB, HIST_BT>), dim3(hg), dim3(HIST_BT), 0, st, w, Lc);
+            if (j == 0 && pairs) {
+                if constexpr (!LB && K >= 4)
+                    hipLaunchKernelGGL((k_hist<KB, K, false, HIST_BT, true>), dim3(hg), dim3(HIST_BT), 0, st, w, Lc,
+                                       j);
+            } else {
+                hipLaunchKernelGGL((k_hist<KB, K, LB, HIST_BT, false>), dim3(hg), dim3(HIST_BT), 0, st, w, Lc, j);
+            }
+        }
+        if (j == 0 && pairs) {
+            Timed tm(st, "k_pair_sum", j);
+            constexpr uint32_t words = (1u << K) * (1u << K) / 2u;
+            hipLaunchKernelGGL(k_pair_sum<K>, dim3(std::max(1u, std::min(1024u, words / THREADS))), dim3(THREADS), 0,
+                               st, w);
         }
         {
             Timed tm(st, "k_pscan", j);
-            hipLaunchKernelGGL((k_pscan<K>), dim3(qg), dim3(THREADS), 0, st, w, Lc);
+            hipLaunchKernelGGL((k_pscan<K>), dim3(qg), dim3(THREADS), 0, st, w, Lc, j);
         }
         {
             Timed tm(st, "k_plan", j);
@@ -255,7 +278,7 @@ int enqueue(Work w, const Layout &L, const uint32_t *seg_off, uint32_t nseg, uin
         }
         {
             Timed tm(st, "k_scatter", j);
-            hipLaunchKernelGGL((k_scatter<KB, K, SBT, SIT, PAY, LB>), dim3(sg), dim3(SBT), 0, st, w, Lc);
+            hipLaunchKernelGGL((k_scatter<KB, K, SBT, SIT, PAY, LB>), dim3(sg), dim3(SBT), 0, st, w, Lc, j);
         }
     }
     {
@@ -334,11 +357,11 @@ int enqueue_inplace(Work w, const Layout &L, char *ws, uint32_t n, hipStream_t s
         const int Lc = j & 1;
         {
             Timed tm(st, "k_hist", j);
-            hipLaunchKernelGGL((k_hist<KB, K, false, HIST_BT>), dim3(lg), dim3(HIST_BT), 0, st, w, Lc);
+            hipLaunchKernelGGL((k_hist<KB, K, false, HIST_BT, false>), dim3(lg), dim3(HIST_BT), 0, st, w, Lc, j);
         }
         {
             Timed tm(st, "k_pscan", j);
-            hipLaunchKernelGGL((k_pscan<K>), dim3(qg), dim3(THREADS), 0, st, w, Lc);
+            hipLaunchKernelGGL((k_pscan<K>), dim3(qg), dim3(THREADS), 0, st, w, Lc, j);
         }
         {
             Timed tm(st, "k_plan", j);

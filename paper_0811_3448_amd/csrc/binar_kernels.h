@@ -70,6 +70,7 @@ constexpr unsigned ERR_SEGMENTS = 1u;  // bad segment table
 constexpr unsigned ERR_INTERNAL = 2u;  // broken invariant (bounds, wait limit)
 
 // A live segment of a global pass.  info = bitpos | parity << 8 | flags << 16
+// | (in a pass whose counts came with pass 0's) its digit in pass 0 << 24
 struct SegEntry {
     uint32_t begin, len, info, tile_start;
 };
@@ -97,7 +98,9 @@ struct Ctl {
     unsigned long long small_keys;   // keys and sub-arrays of k_finish_small
     unsigned long long small_segs;
     unsigned int small_ctr;          // entries of the small list
-    unsigned int pad2;
+    unsigned int fused_pass;         // pass whose digit counts came with pass 0's (0: none)
+    unsigned int fuse_bad;           // pass 0's digit-pair counts overflowed a 16-bit bin
+    unsigned int pad3;
 };
 
 // A range [begin, begin + len) to copy from B to A after the passes.
@@ -129,6 +132,9 @@ struct Work {
     uint32_t nbits;                // leading key bits to sort by (the key width unless limited)
     uint32_t kind;                 // KIND_*: how key bits are ordered; loads apply enc, stores dec
     uint32_t inplace;              // passes permute inside A (no B); small children are not listed
+    uint32_t pair_rows;            // pass 0 also counts digit pairs (blocks of k_hist that may write a row)
+    uint32_t *pair_part;           // [block][R * R / 2]: each k_hist block's pair counts, two 16-bit bins a word
+    uint32_t *pair_sum;            // [R][R]: pair counts of the whole array (digit of pass 0, digit of pass 1)
     void *keys[2];                 // A, B
     uint32_t *pay[2];              // A, B (NULL without payload)
 };
@@ -279,10 +285,13 @@ static __global__ void k_reset(Ctl *ctl) {
 // CAT_SMALL = small list, -1 = none.  Each category reserves one contiguous
 // range with one atomic; next-pass entries reserve their list slots and
 // tiles together, so the list stays ordered by tile_start.  s_base holds
-// S_BASE_WORDS words; word NCLASS + 2 is left to the caller.
+// S_BASE_WORDS words; word NCLASS + 2 is left to the caller.  slot_out, if
+// given, receives the thread's slot in the next list (~0u if it appended
+// none there).
 template <int R>
 __device__ void block_append(const Work &w, int Lnext, int cat, uint32_t begin, uint32_t len, uint32_t bitpos,
-                             uint32_t parity, uint32_t *s_tmp, uint32_t *s_base) {
+                             uint32_t parity, uint32_t *s_tmp, uint32_t *s_base, uint32_t *slot_out = nullptr) {
+    if (slot_out) *slot_out = ~0u;
     uint32_t idx[NCLASS + 2];
     uint32_t tot[NCLASS + 2];
 #pragma unroll
@@ -350,6 +359,7 @@ __device__ void block_append(const Work &w, int Lnext, int cat, uint32_t begin, 
         const uint32_t slot = s_base[NCLASS] + idx[NCLASS];
         const uint32_t ts = s_base[NCLASS + 1] + tidx;
         if (slot < w.max_big && ts + ntiles <= w.max_tiles) {
+            if (slot_out) *slot_out = slot;
             w.list[Lnext][slot] = SegEntry{begin, len, bitpos | (parity << 8), ts};
             unsigned long long *ao = w.andor[Lnext] + (size_t)slot * 4;
             w.desc[Lnext][slot] = 0u;
@@ -493,8 +503,16 @@ __device__ __forceinline__ typename KeyT<KB>::V raw_key(typename KeyT<KB>::V v, 
 // Also resets the next list and the scatter ticket (nothing else touches
 // them during this kernel) and, for the look-back scatter, clears the
 // look-back words of every tile.
-template <int KB, int K, bool LOOKBACK, int BT>
-__global__ __launch_bounds__(BT) void k_hist(Work w, int L) {
+//
+// PAIRS (first pass of one array): the digit of the next K bits is counted
+// too, per pair (this digit, next digit), in 16-bit LDS bins packed two to a
+// word; each block leaves its pair counts in its row of w.pair_part (and
+// k_pair_sum adds the rows).  A bin that would pass 65535 sets
+// ctl->fuse_bad: the pair counts are then not used (the piece counts come
+// from the exact per-wave counts either way).
+// A pass whose counts came with pass 0's (ctl->fused_pass) reads no key.
+template <int KB, int K, bool LOOKBACK, int BT, bool PAIRS>
+__global__ __launch_bounds__(BT) void k_hist(Work w, int L, int pass) {
     using KT = KeyT<KB>;
     using V = typename KT::V;
     constexpr int R = 1 << K;
@@ -502,6 +520,7 @@ __global__ __launch_bounds__(BT) void k_hist(Work w, int L) {
     constexpr int U = 4;  // vectors in flight per thread
     constexpr int NW = BT / WAVE;
     __shared__ uint32_t s_h[NW][R];
+    __shared__ uint32_t s_p[PAIRS ? R * R / 2 : 1];
     __shared__ unsigned long long s_ao[NW][4];
 
     Ctl *ctl = w.ctl;
@@ -510,6 +529,7 @@ __global__ __launch_bounds__(BT) void k_hist(Work w, int L) {
         ctl->list_ctr[L ^ 1] = 0ull;
         ctl->ticket = 0u;
     }
+    if (pass != 0 && (uint32_t)pass == ctl->fused_pass) return;
     const unsigned long long lc = ctl->list_ctr[L];
     const uint32_t nslots = (uint32_t)(lc >> 32), ntiles = (uint32_t)lc;
     if (ntiles == 0) return;
@@ -519,10 +539,13 @@ __global__ __launch_bounds__(BT) void k_hist(Work w, int L) {
     if (t0 >= t1) return;
 
     const int wv = threadIdx.x / WAVE, lane = lane_id();
+    if (PAIRS)
+        for (int i = threadIdx.x; i < R * R / 2; i += BT) s_p[i] = 0u;
     for (int i = threadIdx.x; i < NW * R; i += BT) (&s_h[0][0])[i] = 0u;
     if (LOOKBACK)
         for (size_t i = (size_t)t0 * R + threadIdx.x; i < (size_t)t1 * R; i += BT) w.status[i] = 0u;
     __syncthreads();
+    bool pair_full = false;  // a pair bin of this thread's reached 65535
 
     uint32_t slot = find_slot(w.list[L], nslots, t0);
     for (uint32_t t = t0; t < t1;) {
@@ -544,8 +567,17 @@ __global__ __launch_bounds__(BT) void k_hist(Work w, int L) {
         // the active lanes and of those whose bit is 1, added to the wave's
         // counters by its first active lane (the loops below are divergent);
         // wider digits with a per-wave LDS histogram
+        // the next digit of the pairs: the K bits after this pass's (the
+        // pairs are used only if the next pass starts there)
+        const int nbits2 = min(K, (int)w.nbits - (int)bitpos - wbits);
         auto count = [&](const V &v) {
             const uint32_t d = KT::digit(v, bitpos, wbits);
+            if constexpr (PAIRS) {
+                const uint32_t b = d * R + (nbits2 > 0 ? KT::digit(v, bitpos + wbits, nbits2) : 0u);
+                const uint32_t sh = (b & 1u) * 16u;
+                const uint32_t old = atomicAdd(&s_p[b >> 1], 1u << sh);
+                pair_full |= ((old >> sh) & 0xFFFFu) == 0xFFFFu;
+            }
             if constexpr (K == 1) {
                 const uint64_t act = __ballot(true), ones = __ballot(d != 0u);
                 if (lane == __builtin_ctzll(act)) {
@@ -636,6 +668,16 @@ __global__ __launch_bounds__(BT) void k_hist(Work w, int L) {
             }
             row[d] = c;
         }
+        if constexpr (PAIRS) {
+            // one piece per block (one array): the pairs go to the block's
+            // row, cleared after
+            uint32_t *prow = w.pair_part + (size_t)blockIdx.x * (R * R / 2);
+            for (int i = threadIdx.x; i < R * R / 2; i += BT) {
+                prow[i] = s_p[i];
+                s_p[i] = 0u;
+            }
+            if (__syncthreads_or(pair_full ? 1 : 0) && threadIdx.x == 0) atomicOr(&ctl->fuse_bad, 1u);
+        }
         if (threadIdx.x < 4) {
             unsigned long long v = s_ao[0][threadIdx.x];
             for (int q = 1; q < NW; ++q)
@@ -652,13 +694,51 @@ __global__ __launch_bounds__(BT) void k_hist(Work w, int L) {
     }
 }
 
+// -------------------------------------------------------------- k_pair_sum
+// Pair counts of the whole array: the sum of the rows that k_hist's blocks
+// with work left in w.pair_part (block b has work iff b * per < tiles),
+// unpacked to 32 bits, into w.pair_sum[d0 * R + d1].
+template <int K>
+__global__ __launch_bounds__(THREADS) void k_pair_sum(Work w) {
+    constexpr int R = 1 << K;
+    constexpr uint32_t NPW = R * R / 2;  // words per row
+    Ctl *ctl = w.ctl;
+    if (ctl->error | ctl->overflow | ctl->fuse_bad) return;
+    const unsigned long long lc = ctl->list_ctr[0];
+    const uint32_t ntiles = (uint32_t)lc;
+    if (ntiles == 0 || (uint32_t)(lc >> 32) != 1u) return;
+    const uint32_t per = (ntiles + w.chunk_grid - 1) / w.chunk_grid;
+    const uint32_t rows = min(w.pair_rows, (ntiles + per - 1) / per);
+    for (uint32_t i = blockIdx.x * THREADS + threadIdx.x; i < NPW; i += gridDim.x * THREADS) {
+        uint32_t lo = 0u, hi = 0u;
+        uint32_t b = 0;
+        for (; b + 8 <= rows; b += 8) {
+            uint32_t x[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) x[q] = w.pair_part[(size_t)(b + q) * NPW + i];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                lo += x[q] & 0xFFFFu;
+                hi += x[q] >> 16;
+            }
+        }
+        for (; b < rows; ++b) {
+            const uint32_t x = w.pair_part[(size_t)b * NPW + i];
+            lo += x & 0xFFFFu;
+            hi += x >> 16;
+        }
+        w.pair_sum[2 * i] = lo;
+        w.pair_sum[2 * i + 1] = hi;
+    }
+}
+
 // ------------------------------------------------------------------ k_pscan
 // For every live segment and digit: the exclusive prefix of its piece counts
 // over the segment's pieces (in tile order, written back in place) and the
 // segment's digit total.  One block per (segment, group of up to 32
 // digits); THREADS / group lanes split the pieces into contiguous runs.
 template <int K>
-__global__ __launch_bounds__(THREADS) void k_pscan(Work w, int L) {
+__global__ __launch_bounds__(THREADS) void k_pscan(Work w, int L, int pass) {
     constexpr int R = 1 << K;
     constexpr int DG = R < 32 ? R : 32;          // digits per block
     constexpr int NG = R / DG;                   // digit groups per segment
@@ -668,6 +748,7 @@ __global__ __launch_bounds__(THREADS) void k_pscan(Work w, int L) {
 
     Ctl *ctl = w.ctl;
     if (ctl->error | ctl->overflow) return;
+    if (pass != 0 && (uint32_t)pass == ctl->fused_pass) return;  // totals set by pass 0's plan, one piece per segment
     const unsigned long long lc = ctl->list_ctr[L];
     const uint32_t nslots = (uint32_t)(lc >> 32), ntiles = (uint32_t)lc;
     if (nslots == 0) return;
@@ -728,11 +809,13 @@ __global__ __launch_bounds__(THREADS) void k_plan(Work w, int L, int pass) {
     __shared__ uint32_t s_tmp[WAVES];
     __shared__ uint32_t s_base[S_BASE_WORDS];
     __shared__ uint32_t s_state[THREADS];
+    __shared__ uint32_t s_max;
     Ctl *ctl = w.ctl;
     if (ctl->error | ctl->overflow) return;
     const unsigned long long lc = ctl->list_ctr[L];
     const uint32_t nslots = (uint32_t)(lc >> 32);
     if (nslots == 0) return;
+    const bool fused_here = pass != 0 && (uint32_t)pass == ctl->fused_pass;  // no key was read for this pass
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicMax(&ctl->passes, (unsigned)(pass + 1));
     const int ps = pass < MAX_PASSES ? pass : MAX_PASSES - 1;
     const int d = threadIdx.x;
@@ -746,11 +829,15 @@ __global__ __launch_bounds__(THREADS) void k_plan(Work w, int L, int pass) {
         const uint32_t bitpos = seg.info & 0xFFu, parity = (seg.info >> 8) & 1u;
         const int wbits = min(K, NB - (int)bitpos);
         const uint32_t nbins = 1u << wbits;
-        const uint32_t c = (d < (int)nbins) ? w.counts[L][(size_t)s * R + d] : 0u;
+        // counts of this segment's digits: from the digit count, or, in the
+        // pass whose counts came with pass 0's, row (parent digit) of the
+        // pair sums
+        const uint32_t *segc = fused_here ? w.pair_sum + (size_t)(seg.info >> 24) * R : w.counts[L] + (size_t)s * R;
+        const uint32_t c = (d < (int)nbins) ? segc[d] : 0u;
         const int nz = __syncthreads_count(c != 0u);
         const unsigned long long *ao = w.andor[L] + (size_t)s * 4;
         const Canon diff{ao[0] ^ ao[2], ao[1] ^ ao[3]};
-        st_hist += seg.len;
+        if (!fused_here) st_hist += seg.len;
 
         if (w.desc[L][s] == 0u) {
             // already in order (section "Optimize the Algorithm": a sorted
@@ -828,7 +915,7 @@ __global__ __launch_bounds__(THREADS) void k_plan(Work w, int L, int pass) {
                 while (e >= 0 && s_state[e] == 0u) --e;
                 head = (e < 0) || (s_state[e] == 2u);
                 if (head) {
-                    for (int f = d; f < R && s_state[f] != 2u; ++f) run += w.counts[L][(size_t)s * R + f];
+                    for (int f = d; f < R && s_state[f] != 2u; ++f) run += segc[f];
                 }
             }
             uint32_t nh;
@@ -843,7 +930,39 @@ __global__ __launch_bounds__(THREADS) void k_plan(Work w, int L, int pass) {
                     atomicOr(&ctl->overflow, 1u);
             }
         }
-        block_append<R>(w, L ^ 1, cat, seg.begin + excl, c, cb, child_parity, s_tmp, s_base);
+        uint32_t slot = ~0u;
+        block_append<R>(w, L ^ 1, cat, seg.begin + excl, c, cb, child_parity, s_tmp, s_base, &slot);
+        if (pass == 0 && w.pair_rows != 0u && nslots == 1u && !w.inplace) {
+            // the next pass takes its digit counts from pass 0's pair counts
+            // if they hold (no bin overflowed, every child's next digit
+            // starts right after this one) and one whole child per scatter
+            // block balances the work: as many children as blocks at most,
+            // the largest within 1/8 of an even share of the tiles
+            const uint32_t nt = (cat == NCLASS) ? (c + w.tile_keys - 1) / w.tile_keys : 0u;
+            uint32_t tt, nn;
+            (void)block_excl_scan(nt, s_tmp, &tt);
+            (void)block_excl_scan(cat == NCLASS ? 1u : 0u, s_tmp, &nn);
+            if (d == 0) s_max = 0u;
+            __syncthreads();
+            if (nt) atomicMax(&s_max, nt);
+            __syncthreads();
+            const uint32_t even = (tt + w.chunk_grid - 1) / w.chunk_grid;
+            const bool fuse = nn != 0u && nn <= w.chunk_grid && s_max <= even + even / 8u &&
+                              first_set_from(diff, bitpos + wbits, NB) == (int)bitpos + wbits &&
+                              ctl->fuse_bad == 0u;
+            if (fuse) {
+                if (d == 0) ctl->fused_pass = (uint32_t)pass + 1u;
+                if (slot != ~0u) {
+                    // the child's digit here tags it (its counts are row d of
+                    // the pair sums); sortedness unknown; the constant bits of
+                    // the parent are constant in the child
+                    w.list[L ^ 1][slot].info |= (uint32_t)d << 24;
+                    w.desc[L ^ 1][slot] = 1u;
+                    unsigned long long *cao = w.andor[L ^ 1] + (size_t)slot * 4;
+                    for (int q = 0; q < 4; ++q) cao[q] = ao[q];
+                }
+            }
+        }
     }
     if (d == 0) {
         if (st_hist) atomicAdd(&ctl->hist_keys[ps], st_hist);
@@ -1133,8 +1252,12 @@ __device__ __forceinline__ void flush_carry(const Work &w, ScatterLds<KB, K, BT,
     __syncthreads();
 }
 
+// A pass whose digit counts came with pass 0's (ctl->fused_pass) has no
+// piece counts: block b takes the whole segment in slot b of the list (the
+// plan chose this only for at most as many, evenly sized, segments as
+// blocks), starting at the segment's bucket bases.
 template <int KB, int K, int BT, int ITEMS, bool PAY, bool LOOKBACK>
-__global__ __launch_bounds__(BT) void k_scatter(Work w, int L) {
+__global__ __launch_bounds__(BT) void k_scatter(Work w, int L, int pass) {
     using V = typename KeyT<KB>::V;
     constexpr int R = 1 << K;
     constexpr uint32_t TILE = BT * ITEMS;
@@ -1146,11 +1269,18 @@ __global__ __launch_bounds__(BT) void k_scatter(Work w, int L) {
     const unsigned long long lc = ctl->list_ctr[L];
     const uint32_t nslots = (uint32_t)(lc >> 32), ntiles = (uint32_t)lc;
     if (ntiles == 0) return;
+    const bool whole = !LOOKBACK && pass != 0 && (uint32_t)pass == ctl->fused_pass;
     uint32_t t0 = 0, t1 = 0;
     if (!LOOKBACK) {
-        const uint32_t per = (ntiles + gridDim.x - 1) / gridDim.x;
-        t0 = blockIdx.x * per;
-        t1 = min(ntiles, t0 + per);
+        if (whole) {
+            if (blockIdx.x >= nslots) return;
+            t0 = w.list[L][blockIdx.x].tile_start;
+            t1 = seg_tile_end(w.list[L], blockIdx.x, nslots, ntiles);
+        } else {
+            const uint32_t per = (ntiles + gridDim.x - 1) / gridDim.x;
+            t0 = blockIdx.x * per;
+            t1 = min(ntiles, t0 + per);
+        }
         if (t0 >= t1) return;
     }
     for (int i = threadIdx.x; i < NW * R; i += BT) (&S.wh[0][0])[i] = 0u;
@@ -1186,7 +1316,7 @@ __global__ __launch_bounds__(BT) void k_scatter(Work w, int L) {
     V keyn[ITEMS];
     uint32_t payn[ITEMS];
     uint32_t t = t0;
-    uint32_t slot = uni(find_slot(w.list[L], nslots, t));
+    uint32_t slot = whole ? blockIdx.x : uni(find_slot(w.list[L], nslots, t));
     SegEntry seg = uni(w.list[L][slot]);
     uint32_t seg_end = uni(seg_tile_end(w.list[L], slot, nslots, ntiles));
     bool loaded = false;
@@ -1202,7 +1332,8 @@ __global__ __launch_bounds__(BT) void k_scatter(Work w, int L) {
                 continue;
             }
             if (threadIdx.x < R) {
-                S.run[threadIdx.x] = w.bases[L][(size_t)slot * R + threadIdx.x] + w.pcnt[(size_t)t * R + threadIdx.x];
+                S.run[threadIdx.x] =
+                    w.bases[L][(size_t)slot * R + threadIdx.x] + (whole ? 0u : w.pcnt[(size_t)t * R + threadIdx.x]);
                 S.cc[threadIdx.x] = 0u;
             }
             load_tile<KB, BT, ITEMS, PAY>(w, seg, t, key, pay);
