@@ -112,6 +112,8 @@ def copy_ceiling(torch, dev, nbytes: int = 2 << 30, reps: int = 5):
 
 
 def cpu_baseline(keys_np, log2_sample: int):
+    """The oracle (recursive stable binar partition in C) on one host core,
+    on the first 2^log2_sample keys of the workload with an index payload."""
     import numpy as np
     import oracle
     n = min(keys_np.shape[0], 1 << log2_sample)
@@ -124,6 +126,31 @@ def cpu_baseline(keys_np, log2_sample: int):
     return {"value": n / dt / 1e9, "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
             "sample": "first 2^%d keys (+ index payload) of the same workload, recursive stable binar "
                       "partition in C on one host core, %.1f s" % (log2_sample, dt)}
+
+
+def cpu_more_baselines(keys_np, log2_sample: int) -> dict:
+    """Two more host references on the same sample: std::stable_sort on one
+    core, and the paper's parallel variant (one stable partition on the
+    leading byte, then the buckets by the oracle on every core this process
+    may use, at most 16)."""
+    import numpy as np
+    import oracle
+    n = min(keys_np.shape[0], 1 << log2_sample)
+    k = keys_np[:n].copy()
+    p = np.arange(n, dtype=np.uint32)
+    t0 = time.perf_counter()
+    oracle.stable_sort_ref(k, p)
+    dt_s = time.perf_counter() - t0
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    t0 = time.perf_counter()
+    oracle.parallel_sort_ref(k, p, cores)
+    dt_p = time.perf_counter() - t0
+    return {"cpu_stable_sort": {"value": n / dt_s / 1e9, "unit": "Gkeys/s", "cores": 1, "kind": "std::stable_sort",
+                                "sample": "first 2^%d keys (+ index payload), %.1f s" % (log2_sample, dt_s)},
+            "cpu_parallel_variant": {"value": n / dt_p / 1e9, "unit": "Gkeys/s", "cores": cores,
+                                     "kind": "leading-byte partition, then the oracle per bucket on %d threads"
+                                             % cores,
+                                     "sample": "first 2^%d keys (+ index payload), %.1f s" % (log2_sample, dt_p)}}
 
 
 def choose_params(binar, args, kb, has_pay, n, batched):
@@ -168,10 +195,11 @@ def offs_of(off_np):
     return off_np.astype("int64").tolist()
 
 
-def bench_batched(args) -> int:
+def measure_batched(args, per_array: bool = True) -> dict:
     """Batched workload: 100,000 lognormal segments of u32 keys (+ global
     index payload), about 2^27 keys.  One HIP-graph replay of the segmented
-    sort against one plain library call per array on the same GPU."""
+    sort (median of the timed replays) against one plain library call per
+    array on the same GPU (measured once)."""
     import numpy as np
     import torch
     import paper_0811_3448_amd as binar
@@ -209,6 +237,18 @@ def bench_batched(args) -> int:
     st = plan.stats()
     if st["status"] != 0:
         raise RuntimeError("batched sort status %d" % st["status"])
+    # the last replay's output, checked on the device: every segment sorted,
+    # its payload a permutation of its own indices, ties in index order
+    seg = torch.repeat_interleave(torch.arange(S, device=dev), torch.diff(off.to(torch.int64)), output_size=n)
+    u = kbuf.to(torch.int64) & 0xFFFFFFFF
+    same = seg[1:] == seg[:-1]
+    p = pbuf.to(torch.int64)
+    ok = bool((u[1:] >= u[:-1])[same].all()) and bool((p[1:] > p[:-1])[same & (u[1:] == u[:-1])].all())
+    ok = ok and torch.equal(torch.sort(p).values, torch.arange(n, device=dev)) and torch.equal(
+        pristine.to(torch.int64)[p] & 0xFFFFFFFF, u) and bool((seg[p] == seg).all())
+    if not ok:
+        raise RuntimeError("batched output check failed")
+    del seg, u, same, p
     graph_ms = float(np.median(times))
 
     # per-kernel breakdown: one eager call of the same sort, each launch
@@ -228,35 +268,46 @@ def bench_batched(args) -> int:
     st_e = binar.stats(ws_b)
     del ws_b
 
-    if args.no_per_array:
-        per_array_ms = per_array_wall = None
-    else:
+    per_array_ms = per_array_wall = None
+    if per_array:
         per_array_ms, per_array_wall = per_array_calls(binar, torch, kbuf, pbuf, restore, offs_of(off_np),
                                                        S, params, stream, np)
-    result = {
-        "metric": "Gkeys/s, batched segmented sort of 100,000 arrays in one graph replay",
-        "value": round(n / (graph_ms * 1e-3) / 1e9, 3), "unit": "Gkeys/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(graph_ms, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
-        "data": "synthetic",
-        "config": {"workload": "batched_u32_100k: %d lognormal segments (median 1024, sigma 0.7356), %d u32 keys "
-                               "+ u32 index payload" % (S, n), "segments": S, "n": n,
-                   **describe_params(binar, 4, True, params, source)},
+    plan.close()
+    return {
+        "graph_ms": round(graph_ms, 4), "gkeys_s": round(n / (graph_ms * 1e-3) / 1e9, 3),
+        "segments": S, "n": n, **describe_params(binar, 4, True, params, source),
         "per_array_calls": None if per_array_ms is None else {
             "ms": round(per_array_ms, 2), "gkeys_s": round(n / (per_array_ms * 1e-3) / 1e9, 3),
-            "host_wall_s": round(per_array_wall, 2)},
+            "host_wall_s": round(per_array_wall, 2), "measured": "once, every array by one library call"},
         "speedup_vs_per_array": None if per_array_ms is None else round(per_array_ms / graph_ms, 2),
         "finish_segments": st["finish_segments"], "passes": st["passes"],
         "eager_kernels_ms": kernels,
         "finish_class_segments": st_e["finish_class_segments"], "finish_class_keys": st_e["finish_class_keys"],
         "finish_small_segments": st_e["finish_small_segments"],
     }
+
+
+def bench_batched(args) -> int:
+    r = measure_batched(args, per_array=not args.no_per_array)
+    result = {
+        "metric": "Gkeys/s, batched segmented sort of 100,000 arrays in one graph replay",
+        "value": r["gkeys_s"], "unit": "Gkeys/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["graph_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "batched_u32_100k: %d lognormal segments (median 1024, sigma 0.7356), %d u32 keys "
+                               "+ u32 index payload" % (r["segments"], r["n"]), "segments": r["segments"],
+                   "n": r["n"], "digit_bits": r["digit_bits"], "tile_keys": r["tile_keys"],
+                   "finish_max": r["finish_max"], "offsets": r["offsets"], "params_from": r["params_from"]},
+        **{k: v for k, v in r.items() if k not in ("graph_ms", "gkeys_s", "segments", "n", "digit_bits",
+                                                     "tile_keys", "finish_max", "offsets", "params_from")},
+    }
     print(json.dumps(result), flush=True)
     return 0
 
 
-def bench_serve(args) -> int:
-    """Serving workload: 10,000 sort requests with Poisson arrivals, sizes
+def measure_serve(args, R: int) -> dict:
+    """Serving workload: R sort requests with Poisson arrivals, sizes
     lognormal (median 2^16, sigma 2 ln 2, clipped to [2^8, 2^24]), key widths
     u32 / u64 / 16-byte strings = 50 / 30 / 20 % (strings: a lowercase prefix
     of 0..12 bytes shared by the request, the rest lowercase), each answered
@@ -265,7 +316,9 @@ def bench_serve(args) -> int:
     A saturating run (all requests at once) calibrates the rate: the timed
     runs use 0.7 of its request rate, once with continuous batching
     (segmented graph replays, two streams per width) and once with one
-    request per launch in arrival order."""
+    request per launch in arrival order.  A last, untimed run of the same
+    requests checks every answer on the device (sorted, the permutation a
+    permutation, keys following it, ties in input order)."""
     import numpy as np
     import torch
     import workloads
@@ -274,7 +327,6 @@ def bench_serve(args) -> int:
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    R = args.serve_requests
     trace = workloads.serve_requests(R, rate_per_s=1.0)     # unit rate: arrival times scale with 1/rate
     print("bench: serve pools", file=sys.stderr, flush=True)
     pool_n = 1 << 24
@@ -296,9 +348,12 @@ def bench_serve(args) -> int:
     def lookup(kb, cap):
         return cache.lookup(kb, True, cap, True, max_distance=4)
 
+    def make_server(batching):
+        return Server(budget_bytes=args.serve_budget_gib << 30, streams=2, max_batch_keys=1 << 25,
+                      max_batch_requests=1024, batching=batching, params_lookup=lookup)
+
     def run(batching, rate):
-        srv = Server(budget_bytes=args.serve_budget_gib << 30, streams=2, max_batch_keys=1 << 25,
-                     max_batch_requests=1024, batching=batching, params_lookup=lookup)
+        srv = make_server(batching)
         warm = [srv.submit(pools[k][:4096]) for k in ((4, 0), (8, 0), (16, 0)) for _ in range(2)]
         for f in warm:
             f.result()
@@ -317,11 +372,51 @@ def bench_serve(args) -> int:
         srv.close()
         return srv.report()
 
+    def check_all():
+        """Every request once more through the batching server (untimed),
+        each answer checked on the device as it completes."""
+        srv = make_server(True)
+        futs = [srv.submit(r) for r in reqs]
+        bad = 0
+        for i, r in enumerate(reqs):
+            res = futs[i].result()
+            futs[i] = None    # each answer is dropped once checked
+            kin = r.to(dev, non_blocking=True)
+            p = res.perm.to(torch.int64)
+            n = kin.shape[0]
+            if kin.dim() == 2:       # 16-byte strings: compare as two big-endian 64-bit halves
+                be = kin.view(torch.uint8).reshape(n, 16).to(torch.int64)
+                w = torch.stack([(be[:, i * 8:(i + 1) * 8] << torch.arange(56, -8, -8, device=dev)).sum(1)
+                                 for i in range(2)], 1)
+                ko = res.keys.view(torch.uint8).reshape(n, 16).to(torch.int64)
+                wo = torch.stack([(ko[:, i * 8:(i + 1) * 8] << torch.arange(56, -8, -8, device=dev)).sum(1)
+                                  for i in range(2)], 1)
+                flip = -(1 << 63)
+                a, b = wo[:-1] ^ flip, wo[1:] ^ flip
+                order = (a[:, 0] < b[:, 0]) | ((a[:, 0] == b[:, 0]) & (a[:, 1] <= b[:, 1]))
+                tie = (a[:, 0] == b[:, 0]) & (a[:, 1] == b[:, 1])
+                follows = torch.equal(w[p], wo)
+            else:
+                u_in = kin.to(torch.int64) & 0xFFFFFFFF if kin.dtype == torch.int32 else kin ^ (-(1 << 63))
+                u_out = res.keys.to(torch.int64) & 0xFFFFFFFF if kin.dtype == torch.int32 else res.keys ^ (-(1 << 63))
+                order = u_out[1:] >= u_out[:-1]
+                tie = u_out[1:] == u_out[:-1]
+                follows = torch.equal(u_in[p], u_out)
+            ok = bool(order.all()) and follows and torch.equal(torch.sort(p).values, torch.arange(n, device=dev))
+            ok = ok and bool((p[1:] > p[:-1])[tie].all())
+            bad += 0 if ok else 1
+        srv.close()
+        return bad
+
     sat = run(True, None)
     # requests per second of the saturating run (first submission to last completion)
     rate = 0.7 * sat["throughput_keys_s"] / (total_keys / R)
     batched = run(True, rate)
     fifo = run(False, rate)
+    print("bench: serve: checking every answer", file=sys.stderr, flush=True)
+    bad = check_all()
+    if bad:
+        raise RuntimeError("serving: %d of %d answers failed the check" % (bad, R))
 
     def fmt(rep):
         return {"p50_ms": round(rep["p50_s"] * 1e3, 3), "p99_ms": round(rep["p99_s"] * 1e3, 3),
@@ -331,21 +426,74 @@ def bench_serve(args) -> int:
                 "batches": rep["batches"], "requests": rep["requests"],
                 "peak_admitted_gib": round(rep["peak_admitted_bytes"] / 2 ** 30, 3),
                 "max_waiting": rep["max_waiting"]}
+    del pools, reqs
+    torch.cuda.empty_cache()
+    return {"requests": R, "keys": total_keys, "rate_req_s": round(rate, 1), "budget_gib": args.serve_budget_gib,
+            "saturated": fmt(sat), "batched": fmt(batched), "one_request_per_launch": fmt(fifo),
+            "answers_checked": R}
+
+
+def bench_serve(args) -> int:
+    r = measure_serve(args, args.serve_requests)
+    b = r["batched"]
     result = {
         "metric": "serving throughput (Gkeys/s) with p50/p99 latency, Poisson sort requests",
-        "value": round(batched["throughput_keys_s"] / 1e9, 3), "unit": "Gkeys/s", "n_gpus": 1,
-        "steps": 1, "warmup": 1, "ms_per_step": round(total_keys / batched["throughput_keys_s"] * 1e3, 3),
+        "value": b["throughput_gkeys_s"], "unit": "Gkeys/s", "n_gpus": 1,
+        "steps": 1, "warmup": 1, "ms_per_step": round(r["keys"] / (b["throughput_gkeys_s"] * 1e9) * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32/u64/u8x16",
         "data": "synthetic",
         "config": {"workload": "serve_c5: %d requests, Poisson at 0.7 x saturated rate, sizes lognormal "
                                "(median 2^16, sigma 2 ln 2) in [2^8, 2^24], u32/u64/16 B = 50/30/20 %%, "
-                               "keys in pinned host memory, u32 index payload" % R,
-                   "requests": R, "keys": total_keys, "rate_req_s": round(rate, 1),
-                   "budget_gib": args.serve_budget_gib},
-        "saturated": fmt(sat), "batched": fmt(batched), "one_request_per_launch": fmt(fifo),
+                               "keys in pinned host memory, u32 index payload" % r["requests"],
+                   "requests": r["requests"], "keys": r["keys"], "rate_req_s": r["rate_req_s"],
+                   "budget_gib": r["budget_gib"]},
+        "saturated": r["saturated"], "batched": r["batched"],
+        "one_request_per_launch": r["one_request_per_launch"], "answers_checked": r["answers_checked"],
     }
     print(json.dumps(result), flush=True)
     return 0
+
+
+def measure_small(args) -> dict:
+    """Single array of 2^16 uniform u32 keys, keys only: the library's plain
+    call (events around each call on the stream, the host's launches
+    included) and a plan's graph replay on the same buffers; medians."""
+    import numpy as np
+    import torch
+    import paper_0811_3448_amd as binar
+    import workloads
+    n = 1 << 16
+    keys = workloads.single_keys("u32_2e16_uniform_keys")
+    dev = torch.device("cuda:0")
+    pristine = torch.from_numpy(keys.view(np.int32)).to(dev)
+    kd = pristine.clone()
+    stream = torch.cuda.current_stream()
+    ws = binar.Workspace(binar.workspace_bytes(4, n, False, 1), device=dev)
+    plan = binar.Plan(4, n, 1, False)
+
+    def timed(fn, reps=30):
+        for _ in range(3):
+            kd.copy_(pristine)
+            fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            kd.copy_(pristine)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+    eager = timed(lambda: binar.sort(kd, workspace=ws))
+    replay = timed(lambda: plan.sort(kd))
+    ok = bool(((kd.to(torch.int64) & 0xFFFFFFFF).diff() >= 0).all())
+    plan.close()
+    if not ok:
+        raise RuntimeError("small sort output not sorted")
+    return {"n": n, "eager_us": round(eager * 1e3, 1), "plan_replay_us": round(replay * 1e3, 1),
+            "what": "2^16 uniform u32 keys only; median of 30 sorts, events on the stream"}
 
 
 def linear_fit(xs, ys):
@@ -530,6 +678,8 @@ def main() -> int:
     ap.add_argument("--workload", default="u32_2e28_uniform")
     ap.add_argument("--cpu-sample-log2", type=int, default=25)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="headline only: skip the 2^16-key, batched and serving measurements")
     ap.add_argument("--digit-bits", type=int, default=0)
     ap.add_argument("--tile-keys", type=int, default=0)
     ap.add_argument("--finish-max", type=int, default=0)
@@ -763,9 +913,19 @@ def main() -> int:
         result["copy_ceiling"] = cc
         result["roofline"]["frac_of_copy"] = round(achieved / cc["gbs"], 4)
         result["sort_roofline"]["frac_of_copy"] = round(total_bytes / (ms_per_step * 1e-3) / 1e9 / cc["gbs"], 4)
+    if not args.no_extras and not args.inplace and name == "u32_2e28_uniform":
+        # the other configurations, measured in the same run
+        print("bench: 2^16 keys", file=sys.stderr, flush=True)
+        result["c1_small"] = measure_small(args)
+        print("bench: 100,000 arrays", file=sys.stderr, flush=True)
+        result["c4_batched"] = measure_batched(args, per_array=not args.no_per_array)
+        print("bench: serving", file=sys.stderr, flush=True)
+        result["c5_serve"] = measure_serve(args, args.serve_requests)
     if not args.no_cpu_baseline:
         print("bench: CPU oracle sample", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(keys_np, args.cpu_sample_log2)
+        print("bench: CPU library and parallel-variant samples", file=sys.stderr, flush=True)
+        result.update(cpu_more_baselines(keys_np, args.cpu_sample_log2))
     print(json.dumps(result), flush=True)
     return 0
 

@@ -15,6 +15,11 @@ Contents
   Formalism" with a stability tie-break), written with Python's sort.
 * ``swap_partition.py``: the paper's own unstable exchange partition, written
   from its prose, used to check the printed worked example.
+* ``baselines.cpp`` (built with g++ together with ``binar_ref.c`` into
+  ``libbinar_baselines.so``): two CPU reference timings for the benchmark,
+  :func:`stable_sort_ref` (``std::stable_sort`` on one thread) and
+  :func:`parallel_sort_ref` (the paper's parallel variant: one stable
+  partition on the leading byte, then the buckets on several threads).
 
 Key arrays: ``uint32`` (4-byte keys), ``uint64`` (8-byte keys) or ``uint8``
 of shape (n, 16) (16-byte strings in memcmp order).  Payloads are ``uint32``.
@@ -30,16 +35,34 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "binar_ref.c")
 _LIB = os.path.join(_HERE, "libbinar_oracle.so")
+_BSRC = os.path.join(_HERE, "baselines.cpp")
+_BLIB = os.path.join(_HERE, "libbinar_baselines.so")
 _lib = None
+_blib = None
+
+
+def _stale(lib, *srcs):
+    return not os.path.exists(lib) or any(os.path.getmtime(lib) < os.path.getmtime(s) for s in srcs)
 
 
 def build(force: bool = False) -> str:
-    """Compile the C oracle with gcc (seconds); returns the library path."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    """Compile the C oracle with gcc and the CPU baselines with g++ (seconds);
+    returns the oracle library's path."""
+    if force or _stale(_LIB, _SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC",
                                "-o", tmp, _SRC])
         os.replace(tmp, _LIB)
+    if force or _stale(_BLIB, _SRC, _BSRC):
+        tmp = _BLIB + ".tmp%d" % os.getpid()
+        obj = tmp + ".o"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-c", "-o", obj, _SRC])
+        try:
+            subprocess.check_call(["g++", "-O2", "-std=c++17", "-Wall", "-Wextra", "-shared", "-fPIC", "-pthread",
+                                   "-o", tmp, _BSRC, obj])
+        finally:
+            os.remove(obj)
+        os.replace(tmp, _BLIB)
     return _LIB
 
 
@@ -120,4 +143,34 @@ def sort_segmented(keys: np.ndarray, seg_offsets: np.ndarray, payload: np.ndarra
     off = np.ascontiguousarray(seg_offsets, dtype=np.uint64)
     _check(_L().binar_sort_segmented_ref(k.ctypes.data, key_bytes_of(k), off.ctypes.data,
                                          off.shape[0] - 1, _pp(p)))
+    return k, p
+
+
+def _B():
+    global _blib
+    if _blib is None:
+        build()
+        lib = ctypes.CDLL(_BLIB)
+        vp, u32, u64 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64
+        lib.ref_stable_sort.argtypes = [vp, u32, u64, vp]
+        lib.ref_parallel_binar.argtypes = [vp, u32, u64, vp, ctypes.c_int]
+        lib.ref_stable_sort.restype = ctypes.c_int
+        lib.ref_parallel_binar.restype = ctypes.c_int
+        _blib = lib
+    return _blib
+
+
+def stable_sort_ref(keys: np.ndarray, payload: np.ndarray | None = None):
+    """CPU baseline: std::stable_sort of (key, payload) pairs on one thread."""
+    k, p = _prep(keys, payload)
+    _check(_B().ref_stable_sort(k.ctypes.data, key_bytes_of(k), k.shape[0], _pp(p)))
+    return k, p
+
+
+def parallel_sort_ref(keys: np.ndarray, payload: np.ndarray | None = None, threads: int = 1):
+    """CPU baseline: the paper's parallel variant (one stable partition on the
+    leading byte, then each bucket by the oracle's binar sort, on ``threads``
+    threads)."""
+    k, p = _prep(keys, payload)
+    _check(_B().ref_parallel_binar(k.ctypes.data, key_bytes_of(k), k.shape[0], _pp(p), int(threads)))
     return k, p
