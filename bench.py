@@ -425,6 +425,7 @@ def measure_serve(args, R: int) -> dict:
                 "requests_per_s": round(rep["requests"] * rep["throughput_keys_s"] / rep["keys"], 1),
                 "batches": rep["batches"], "requests": rep["requests"],
                 "peak_admitted_gib": round(rep["peak_admitted_bytes"] / 2 ** 30, 3),
+                "lanes_gib": round(rep["lane_bytes"] / 2 ** 30, 3), "failed_batches": rep["failed_batches"],
                 "max_waiting": rep["max_waiting"]}
     del pools, reqs
     torch.cuda.empty_cache()

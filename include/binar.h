@@ -223,6 +223,15 @@ int binar_plan_create(binar_plan **out, uint32_t key_bytes, uint64_t max_keys, u
 int binar_plan_sort(binar_plan *plan, void *keys, uint32_t *payload, const uint32_t *seg_offsets,
                     uint32_t num_segments, uint64_t n_total, void *stream);
 int binar_plan_stats(binar_plan *plan, void *stream, binar_stats *out);
+/* Enqueue on `stream` a copy of the plan's two device status words (the
+ * error flags and the list-overflow flag of its last sort; both zero after
+ * a good sort) into host_words[0..1], which should be pinned host memory
+ * for the copy to be asynchronous.  The words are valid once the stream
+ * has reached the copy; a nonzero error word with bit 0 set means a bad
+ * segment table (BINAR_EINVAL), anything else nonzero a broken invariant
+ * (BINAR_EDEVICE).  For servers that check every batch without a
+ * synchronous read. */
+int binar_plan_status_async(const binar_plan *plan, void *stream, uint32_t *host_words);
 int binar_plan_graphs(const binar_plan *plan);
 size_t binar_plan_workspace_bytes(const binar_plan *plan);
 void binar_plan_destroy(binar_plan *plan);

@@ -43,3 +43,18 @@ def stable_rank_u(keys: np.ndarray, j: int) -> int:
     input.  One output at a time, for spot checks of very large sorts."""
     kj = keys[j]
     return int(np.count_nonzero(keys < kj)) + int(np.count_nonzero(keys[:j] == kj))
+
+
+def stable_rank_bytes(keys: np.ndarray, j: int) -> int:
+    """Output position of input string j (a row of a uint8 (n, w) array of
+    fixed-length byte strings) under the stable sort: rows that are smaller
+    at their first byte differing from row j, plus rows equal to row j that
+    come earlier in the input.  One output at a time, for spot checks of
+    large sorts."""
+    kj = keys[j]
+    ne = keys != kj[None, :]
+    differs = ne.any(axis=1)
+    first = ne.argmax(axis=1)
+    rows = np.arange(keys.shape[0])
+    smaller = differs & (keys[rows, first] < kj[first])
+    return int(np.count_nonzero(smaller)) + int(np.count_nonzero(~differs[:j]))

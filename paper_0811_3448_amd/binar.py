@@ -66,6 +66,7 @@ def _load():
     L.binar_plan_sort.argtypes = [vp, vp, vp, vp, u32, u64, vp]
     L.binar_plan_stats.argtypes = [vp, vp, ctypes.POINTER(_Stats)]
     L.binar_plan_graphs.argtypes = [vp]
+    L.binar_plan_status_async.argtypes = [vp, vp, vp]
     L.binar_plan_workspace_bytes.argtypes = [vp]
     L.binar_plan_workspace_bytes.restype = sz
     L.binar_plan_destroy.argtypes = [vp]
@@ -85,7 +86,7 @@ def _load():
               "binar_sort_segmented", "binar_sort_ex",
               "binar_stats_read", "binar_get_default_params", "binar_set_default_params", "binar_resolve_params",
               "binar_profile_enable", "binar_profile_read", "binar_plan_create", "binar_plan_sort",
-              "binar_plan_stats", "binar_plan_graphs"):
+              "binar_plan_stats", "binar_plan_graphs", "binar_plan_status_async"):
         getattr(L, f).restype = i32
     return L
 
@@ -348,6 +349,14 @@ def _stats_dict(s: "_Stats") -> dict:
             "finish_small_segments": s.finish_small_segments}
 
 
+def status_of_words(error: int, overflow: int) -> int:
+    """Status code of a sort from its two device status words (the error
+    flags and the list-overflow flag, see binar_plan_status_async)."""
+    if error & 1:
+        return BINAR_EINVAL
+    return BINAR_EDEVICE if (error or overflow) else BINAR_OK
+
+
 class Plan:
     """Reusable sort plan on resident buffers: the first sort with a given
     set of buffers captures a HIP graph, later sorts replay it (see
@@ -388,6 +397,15 @@ class Plan:
         s = _Stats()
         _check(lib.binar_plan_stats(self._h, _stream_ptr(stream), ctypes.byref(s)))
         return _stats_dict(s)
+
+    def status_async(self, host_words, stream=None) -> None:
+        """Enqueue on `stream` a copy of the last sort's two status words
+        into `host_words` (a pinned int32 CPU tensor of two elements); read
+        them with status_of_words once the stream has passed the copy."""
+        if (host_words.is_cuda or host_words.element_size() != 4 or host_words.numel() < 2
+                or not host_words.is_contiguous()):
+            raise ValueError("host_words must be a contiguous 4-byte host tensor of two elements")
+        _check(lib.binar_plan_status_async(self._h, _stream_ptr(stream), ctypes.c_void_p(host_words.data_ptr())))
 
     @property
     def graphs(self) -> int:

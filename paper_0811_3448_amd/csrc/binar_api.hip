@@ -581,6 +581,16 @@ int binar_plan_stats(binar_plan *p, void *stream, binar_stats *out) {
     return binar_stats_read(p->ws, stream, out);
 }
 
+int binar_plan_status_async(const binar_plan *p, void *stream, uint32_t *host_words) {
+    using namespace binar;
+    if (!p || !host_words) return BINAR_EINVAL;
+    // error and overflow are adjacent words of the control block
+    static_assert(offsetof(Ctl, overflow) == offsetof(Ctl, error) + 4, "status words must be adjacent");
+    const char *src = static_cast<const char *>(p->ws) + p->L.ctl + offsetof(Ctl, error);
+    BINAR_HIP_TRY(hipMemcpyAsync(host_words, src, 8, hipMemcpyDeviceToHost, static_cast<hipStream_t>(stream)));
+    return BINAR_OK;
+}
+
 int binar_plan_graphs(const binar_plan *p) { return p ? (int)p->graphs.size() : 0; }
 
 size_t binar_plan_workspace_bytes(const binar_plan *p) { return p ? p->L.total : 0; }

@@ -6,18 +6,30 @@ time through ``Server.submit`` and are answered
 through a ``concurrent.futures.Future`` with the sorted keys and the stable
 sorting permutation (int32 holding uint32 indices into the request).
 
-* Admission: a request costs ``2 * (key_bytes + 4) * n + META_BYTES`` bytes
-  of the HBM budget (its keys and permutation, and their share of the sort's
-  ping-pong scratch).  It is admitted in arrival order while the bytes of
-  admitted, unfinished requests stay within the budget; otherwise it waits.
-  A request that could never fit is refused at submit with BINAR_ENOMEM.
-* Batching: admitted requests of one key width are packed, in admission
-  order, into the resident buffers of a lane (one per stream and width) and
-  sorted as the segments of one segmented sort: one replay of the lane's
-  captured HIP graph.  Lanes run on separate streams, so batches overlap.
-  A lane takes up to ``max_batch_keys`` keys and ``max_batch_requests``
-  requests; whatever has been admitted when a lane frees up goes in.
-* Completion: when a lane's batch has finished, each request's results are
+* Budget: every byte of device memory the server allocates is charged to one
+  HBM budget.  A lane (one stream and key class) holds resident buffers and a
+  plan workspace for ``max_batch_keys`` keys; it is charged when it is
+  created and held until the server closes (``DeviceBackend.lane_cost``).
+  A request costs ``2 * (key_bytes + 4) * n + META_BYTES`` while it is in
+  flight (the batch's output keys and permutation and the temporaries that
+  make them); the outputs handed to the caller are the caller's.
+* Admission: requests are admitted in arrival order while the charged bytes
+  stay within the budget; otherwise they wait.  The first request of a key
+  class also reserves that class's first lane, so every admitted request has
+  a lane to run on; further lanes of a class (up to ``streams``) are created
+  only while the budget has room for them.  A request that could never fit
+  beside the lanes already held is refused with BINAR_ENOMEM (at submit, or
+  when lanes created later leave it no room).
+* Batching: admitted requests of one key class are packed, in admission
+  order, into the resident buffers of a lane and sorted as the segments of
+  one segmented sort: one replay of the lane's captured HIP graph.  Lanes run
+  on separate streams, so batches overlap.  A lane takes up to
+  ``max_batch_keys`` keys and ``max_batch_requests`` requests; whatever has
+  been admitted when a lane frees up goes in.
+* Completion: every batch copies the plan's device status words to pinned
+  host memory behind its sort; when the batch has finished they are read,
+  and a batch whose sort reported an error fails its Futures with that
+  BinarError (the server carries on).  Otherwise each request's results are
   views of that batch's output tensors (keys, permutation); its budget is
   released and its Future set.
 * Cancelling a Future before its batch starts frees its budget.
@@ -79,42 +91,85 @@ class _Req:
 
 
 class Admission:
-    """HBM-budget accounting with a FIFO wait queue (no device work)."""
+    """HBM-budget accounting with a FIFO wait queue (no device work).
+
+    ``in_use`` counts the bytes of admitted, unfinished requests plus the
+    bytes of every lane charged so far (``fixed``, never released).  A class
+    (key width and kind) holds ``lanes[cls]`` charged lanes, of which
+    ``reserved[cls]`` are charged but not yet created."""
 
     def __init__(self, budget: int):
         if budget <= 0:
             raise ValueError("budget must be positive")
         self.budget = int(budget)
         self.in_use = 0
+        self.fixed = 0
         self.peak = 0
         self.waiting: deque = deque()
+        self.lanes = defaultdict(int)
+        self.reserved = defaultdict(int)
 
-    def offer(self, req: _Req) -> None:
-        if req.cost > self.budget:
+    def _lane_need(self, r, lane_cost) -> int:
+        return lane_cost(r.cls) if lane_cost is not None and self.lanes[r.cls] == 0 else 0
+
+    def offer(self, req: _Req, lane_cost=None) -> None:
+        """Queue a request; BINAR_ENOMEM if it can never fit (its cost, plus
+        its class's first lane if none is charged yet, beside the lanes
+        already held)."""
+        if self.fixed + req.cost + self._lane_need(req, lane_cost) > self.budget:
             raise BinarError(BINAR_ENOMEM)
         self.waiting.append(req)
 
-    def admit(self, now: float) -> list:
-        """Admit from the head of the queue while the budget allows; requests
-        cancelled while waiting are dropped without being charged."""
+    def _charge(self, nbytes: int) -> None:
+        self.in_use += nbytes
+        self.peak = max(self.peak, self.in_use)
+
+    def admit(self, now: float, lane_cost=None) -> list:
+        """Admit from the head of the queue while the budget allows.  The
+        first admitted request of a class without a lane also reserves the
+        class's first lane.  Requests cancelled while waiting are dropped
+        without being charged; a head request that lanes charged since its
+        offer leave no room for fails with BINAR_ENOMEM."""
         out = []
         while self.waiting:
             r = self.waiting[0]
             if r.future.cancelled():
                 self.waiting.popleft()
                 continue
-            if self.in_use + r.cost > self.budget:
+            need = self._lane_need(r, lane_cost)
+            if self.fixed + r.cost + need > self.budget:
+                self.waiting.popleft()
+                if r.future.set_running_or_notify_cancel():
+                    r.future.set_exception(BinarError(BINAR_ENOMEM))
+                continue
+            if self.in_use + r.cost + need > self.budget:
                 break
             self.waiting.popleft()
-            self.in_use += r.cost
-            self.peak = max(self.peak, self.in_use)
+            if need:
+                self.fixed += need
+                self.lanes[r.cls] += 1
+                self.reserved[r.cls] += 1
+            self._charge(r.cost + need)
             r.admitted = now
             out.append(r)
         return out
 
+    def take_lane(self, cls, nbytes: int) -> bool:
+        """May a new lane of `cls` be created?  Uses a reserved lane, else
+        charges `nbytes` if the budget has room for them."""
+        if self.reserved[cls] > 0:
+            self.reserved[cls] -= 1
+            return True
+        if self.in_use + nbytes > self.budget:
+            return False
+        self.fixed += nbytes
+        self.lanes[cls] += 1
+        self._charge(nbytes)
+        return True
+
     def release(self, cost: int) -> None:
         self.in_use -= cost
-        assert self.in_use >= 0
+        assert self.in_use >= self.fixed
 
 
 class Server:
@@ -122,13 +177,13 @@ class Server:
 
     def __init__(self, budget_bytes: int = 8 << 30, backend=None, streams: int = 2,
                  max_batch_keys: int = 1 << 25, max_batch_requests: int = 1024, batching: bool = True,
-                 params_lookup=None, check_status: bool = False, clock=time.perf_counter):
+                 params_lookup=None, clock=time.perf_counter):
         self.max_batch_keys = int(max_batch_keys)
         self.max_batch_requests = int(max_batch_requests) if batching else 1
         self.clock = clock
         self.admission = Admission(budget_bytes)
         self.backend = backend if backend is not None else DeviceBackend(
-            streams, self.max_batch_keys, self.max_batch_requests, params_lookup, check_status=check_status)
+            streams, self.max_batch_keys, self.max_batch_requests, params_lookup)
         self._cv = threading.Condition()
         self._ready = defaultdict(deque)   # (key width, key kind) -> admitted requests
         self._inflight: list = []
@@ -137,6 +192,7 @@ class Server:
         self._error = None
         self.records: list = []            # (n, submitted, admitted, launched, done, batch size) per request
         self.batches = 0
+        self.failed_batches = 0
         self.max_waiting = 0
         self._thread = threading.Thread(target=self._loop, name="binar-serve", daemon=True)
         self._thread.start()
@@ -163,7 +219,7 @@ class Server:
                 raise RuntimeError("server failed") from self._error
             req = _Req(self._next_id, keys, kb, n, request_cost(kb, n), fut, self.clock(), kind=key_kind)
             req.ready_event = self.backend.mark_ready(keys)
-            self.admission.offer(req)      # raises BINAR_ENOMEM for a request that can never fit
+            self.admission.offer(req, self.backend.lane_cost)   # BINAR_ENOMEM if it can never fit
             self._next_id += 1
             self.max_waiting = max(self.max_waiting, len(self.admission.waiting))
             self._cv.notify()
@@ -196,10 +252,11 @@ class Server:
             if not lat:
                 return None
             return lat[min(len(lat) - 1, int(round(p / 100.0 * (len(lat) - 1))))]
-        return {"requests": len(lat), "keys": keys, "batches": self.batches,
+        return {"requests": len(lat), "keys": keys, "batches": self.batches, "failed_batches": self.failed_batches,
                 "p50_s": pct(50), "p99_s": pct(99), "max_s": lat[-1] if lat else None,
                 "throughput_keys_s": keys / span if span > 0 else None,
-                "peak_admitted_bytes": self.admission.peak, "max_waiting": self.max_waiting}
+                "peak_admitted_bytes": self.admission.peak, "lane_bytes": self.admission.fixed,
+                "max_waiting": self.max_waiting}
 
     # ------------------------------------------------------------- scheduler
     def _loop(self):
@@ -209,7 +266,7 @@ class Server:
                 progressed = False
                 with self._cv:
                     now = self.clock()
-                    for r in self.admission.admit(now):
+                    for r in self.admission.admit(now, self.backend.lane_cost):
                         self._ready[r.cls].append(r)
                         progressed = True
                     self._drop_cancelled()
@@ -232,13 +289,15 @@ class Server:
                     self.batches += 1
                     progressed = True
                 still = []
-                for h, lane, reqs in self._inflight:
-                    if self.backend.poll(h):
-                        self._complete(h, lane, reqs)
+                for item in self._inflight:
+                    if self.backend.poll(item[0]):
+                        self._complete(*item)
                         progressed = True
                     else:
-                        still.append((h, lane, reqs))
+                        still.append(item)
                 self._inflight = still
+                # hold no finished batch's outputs here: they are the callers' now
+                h = item = batches = lane = reqs = None
                 if not progressed:
                     with self._cv:
                         if self._running or self.admission.waiting or any(self._ready.values()):
@@ -270,7 +329,8 @@ class Server:
         out = []
         for cls, q in self._ready.items():
             while q:
-                lane = self.backend.free_lane(cls)
+                lane = self.backend.free_lane(
+                    cls, lambda c=cls: self.admission.take_lane(c, self.backend.lane_cost(c)))
                 if lane is None:
                     break
                 reqs, keys = [], 0
@@ -288,28 +348,43 @@ class Server:
         return out
 
     def _complete(self, handle, lane, reqs):
-        outs = self.backend.collect(handle)
+        try:
+            outs = self.backend.collect(handle)
+        except BinarError as e:         # the batch's sort reported an error: fail its requests only
+            outs = e
         t = self.clock()
         with self._cv:
             for r in reqs:
                 self.admission.release(r.cost)
             self._cv.notify()
         self.backend.release_lane(lane)
+        if isinstance(outs, BinarError):
+            self.failed_batches += 1
+            for r in reqs:
+                r.future.set_exception(outs)
+            return
         for r, (k, p) in zip(reqs, outs):
             self.records.append((r.n, r.submitted, r.admitted, r.launched, t, len(reqs)))
             r.future.set_result(SortResult(k, p, r.submitted, r.admitted, r.launched, t, len(reqs)))
 
 
+ALLOC_SLACK = 9 << 20
+"""Bytes charged per lane beyond its buffers' sizes: the caching allocator
+may hand out a block up to 1 MiB larger than asked for, and a lane makes up
+to nine live allocations (four resident buffers, four batch outputs and
+temporaries, one spare)."""
+
+
 class _Lane:
-    """Resident buffers of one stream and key width: keys, permutation,
-    segment table (device and pinned host copy), a plan whose graph is
-    captured on the first batch and replayed for every later one."""
+    """Resident buffers of one stream and key class: keys, permutation,
+    segment table (device and pinned host copy), pinned status words, and a
+    plan whose graph is captured on the first batch and replayed for every
+    later one."""
 
     def __init__(self, kb: int, kind: int, cap: int, max_segments: int, device, params):
         import torch
-        from .binar import Params, Plan
+        from .binar import Plan
         self.kb, self.kind, self.cap, self.max_segments = kb, kind, cap, max_segments
-        params = Params(**{**(vars(params) if params is not None else {}), "key_kind": kind})
         self.stream = torch.cuda.Stream(device=device)
         if kb == 16:
             self.keys = torch.empty((cap, 16), dtype=torch.uint8, device=device)
@@ -319,27 +394,51 @@ class _Lane:
         self.iota = torch.arange(cap, dtype=torch.int32, device=device)
         self.off_dev = torch.zeros(max_segments + 1, dtype=torch.int32, device=device)
         self.off_host = torch.zeros(max_segments + 1, dtype=torch.int32, pin_memory=True)
+        self.status = torch.zeros(2, dtype=torch.int32, pin_memory=True)
         self.plan = Plan(kb, cap, max_segments, True, params)
         self.done = torch.cuda.Event()
         self.busy = False
 
+    @staticmethod
+    def resident_bytes(kb: int, cap: int, max_segments: int) -> int:
+        """Device bytes of the buffers above (the plan's workspace aside)."""
+        return cap * (kb + 4 + 4) + 4 * (max_segments + 1)
+
 
 class DeviceBackend:
     """Runs batches on the GPU: lanes are created on first use, up to
-    `streams` per key width."""
+    `streams` per key class, each only once the server has charged it."""
 
-    def __init__(self, streams: int, cap: int, max_segments: int, params_lookup=None, device=None,
-                 check_status: bool = False):
+    def __init__(self, streams: int, cap: int, max_segments: int, params_lookup=None, device=None):
         import torch
         self.torch = torch
-        self.check_status = check_status
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         self.streams, self.cap, self.max_segments = streams, cap, max_segments
         self.params_lookup = params_lookup
         self.lanes = defaultdict(list)     # (key width, key kind) -> lanes
+        self._params = {}
+        self._cost = {}
 
     def thread_init(self):
         self.torch.cuda.set_device(self.device)
+
+    def _lane_params(self, cls):
+        if cls not in self._params:
+            from .binar import Params
+            kb, kind = cls
+            base = None if self.params_lookup is None else self.params_lookup(kb, self.cap)
+            self._params[cls] = Params(**{**(vars(base) if base is not None else {}), "key_kind": kind})
+        return self._params[cls]
+
+    def lane_cost(self, cls) -> int:
+        """Device bytes one lane of `cls` holds: its resident buffers, its
+        plan's workspace and the allocator slack."""
+        if cls not in self._cost:
+            from .binar import workspace_bytes
+            kb = cls[0]
+            ws = workspace_bytes(kb, self.cap, True, self.max_segments, self._lane_params(cls))
+            self._cost[cls] = _Lane.resident_bytes(kb, self.cap, self.max_segments) + ws + ALLOC_SLACK
+        return self._cost[cls]
 
     def mark_ready(self, keys):
         """Device keys: an event on the submitting thread's current stream,
@@ -355,15 +454,16 @@ class DeviceBackend:
         ev.record()
         return ev
 
-    def free_lane(self, cls):
+    def free_lane(self, cls, may_create):
+        """An idle lane of `cls` (marked busy), or a new one when fewer than
+        `streams` exist and may_create() agrees (it charges the lane)."""
         kb, kind = cls
         for lane in self.lanes[cls]:
             if not lane.busy:
                 lane.busy = True
                 return lane
-        if len(self.lanes[cls]) < self.streams:
-            params = None if self.params_lookup is None else self.params_lookup(kb, self.cap)
-            lane = _Lane(kb, kind, self.cap, self.max_segments, self.device, params)
+        if len(self.lanes[cls]) < self.streams and may_create():
+            lane = _Lane(kb, kind, self.cap, self.max_segments, self.device, self._lane_params(cls))
             self.lanes[cls].append(lane)
             lane.busy = True
             return lane
@@ -394,6 +494,7 @@ class DeviceBackend:
             lane.off_dev.copy_(lane.off_host, non_blocking=True)
             lane.pay[:pos].copy_(lane.iota[:pos], non_blocking=True)
             lane.plan.sort(lane.keys, lane.pay, lane.off_dev, stream=lane.stream)
+            lane.plan.status_async(lane.status, stream=lane.stream)
             # one output pair per batch; each request gets views of its range,
             # its permutation made request-local by subtracting its start
             out_keys = lane.keys[:pos].clone()
@@ -411,12 +512,13 @@ class DeviceBackend:
         return handle[0].done.query()
 
     def collect(self, handle):
-        """The batch's per-request outputs.  With check_status the device's
-        status word is read back (a synchronous copy); the server builds every
-        segment table itself, so only an internal error could set it."""
+        """The batch's per-request outputs, once its status words (copied
+        behind the sort, complete with the batch) show no error; otherwise
+        BinarError with the sort's status."""
+        from .binar import status_of_words
         lane, outs = handle
-        if self.check_status:
-            st = lane.plan.stats(stream=lane.stream)
-            if st["status"] != 0:
-                raise BinarError(st["status"])
+        err, ovf = (int(w) & 0xFFFFFFFF for w in lane.status.tolist())
+        st = status_of_words(err, ovf)
+        if st != 0:
+            raise BinarError(st)
         return outs

@@ -489,6 +489,43 @@ def test_stable_rank_planted_mistakes_fail():
     assert [_rank_tie_mistake(keys, j) for j in range(8)] != ranks
 
 
+def _rank_bytes_last_diff_mistake(keys, j):
+    """stable_rank_bytes deciding at the last differing byte instead of the
+    first (a plausible slip)."""
+    kj = keys[j]
+    ne = keys != kj[None, :]
+    differs = ne.any(axis=1)
+    last = keys.shape[1] - 1 - ne[:, ::-1].argmax(axis=1)
+    smaller = differs & (keys[np.arange(keys.shape[0]), last] < kj[last])
+    return int(np.count_nonzero(smaller)) + int(np.count_nonzero(~differs[:j]))
+
+
+def test_stable_rank_bytes_matches_oracle_positions():
+    """16-byte strings from a four-letter alphabet with a shared prefix
+    (long common runs, many equal rows), every element, against the C
+    oracle's positions; and brute force on tiny inputs."""
+    rng = np.random.default_rng(74)
+    keys = rng.integers(0, 4, (3000, 16)).astype(np.uint8)
+    keys[:, :10] = 7
+    keys[1::3] = keys[0]
+    ranks = _ranks_from_oracle(keys)
+    assert [definition.stable_rank_bytes(keys, j) for j in range(keys.shape[0])] == ranks.tolist()
+    for _ in range(30):
+        n = int(rng.integers(1, 7))
+        small = rng.integers(0, 2, (n, 16)).astype(np.uint8)
+        perm = brute_force_stable(small)
+        assert [definition.stable_rank_bytes(small, j) for j in range(n)] == [perm.index(j) for j in range(n)]
+
+
+def test_stable_rank_bytes_planted_mistake_fails():
+    keys = np.zeros((6, 16), dtype=np.uint8)
+    keys[:, 0] = [2, 1, 2, 1, 0, 2]
+    keys[:, 15] = [0, 9, 5, 0, 1, 0]
+    ranks = _ranks_from_oracle(keys).tolist()
+    assert [definition.stable_rank_bytes(keys, j) for j in range(6)] == ranks
+    assert [_rank_bytes_last_diff_mistake(keys, j) for j in range(6)] != ranks
+
+
 def _segments_with_edges(n_seg, seed, total_hint):
     """Offsets with empty and one-key segments among random lengths."""
     rng = np.random.default_rng(seed)

@@ -24,11 +24,13 @@ def np_stable(keys):
 
 
 class HostBackend:
-    """Lanes that finish only when `gate` is set (or at once if gate is None)."""
+    """Lanes that finish only when `gate` is set (or at once if gate is None);
+    each lane costs `lane_bytes` of the budget."""
 
-    def __init__(self, lanes=1, gate=None):
-        self.lanes, self.gate = lanes, gate
+    def __init__(self, lanes=1, gate=None, lane_bytes=0):
+        self.lanes, self.gate, self.lane_bytes = lanes, gate, lane_bytes
         self.busy = {}
+        self.created = {}
         self.batches = []
         self.lane_block = threading.Event()
         self.lane_block.set()
@@ -39,9 +41,16 @@ class HostBackend:
     def mark_ready(self, keys):
         return None
 
-    def free_lane(self, cls):
-        if not self.lane_block.is_set() or self.busy.get(cls, 0) >= self.lanes:
+    def lane_cost(self, cls):
+        return self.lane_bytes
+
+    def free_lane(self, cls, may_create):
+        if not self.lane_block.is_set():
             return None
+        if self.busy.get(cls, 0) >= self.created.get(cls, 0):
+            if self.created.get(cls, 0) >= self.lanes or not may_create():
+                return None
+            self.created[cls] = self.created.get(cls, 0) + 1
         self.busy[cls] = self.busy.get(cls, 0) + 1
         return cls
 
@@ -234,3 +243,93 @@ def test_key_kinds_batch_apart():
     assert sorted(groups) == [[0, 1, 2], [3, 4, 5], [6]]
     with pytest.raises(ValueError):
         Server(1 << 30, backend=HostBackend()).submit(torch.zeros((4, 16), dtype=torch.uint8), key_kind=2)
+
+
+def test_admission_lane_accounting():
+    class R:
+        def __init__(self, cost, cls):
+            from concurrent.futures import Future
+            self.cost, self.cls, self.future = cost, cls, Future()
+    a = Admission(1000)
+    cost = {"x": 300, "y": 400}.get
+    r1, r2, r3 = R(100, "x"), R(100, "x"), R(250, "y")
+    for r in (r1, r2, r3):
+        a.offer(r, cost)
+    # r1 reserves x's first lane (300 + 100), r2 needs no lane (100); r3
+    # needs y's first lane as well (400 + 250): 500 + 650 > 1000, it waits
+    assert a.admit(0.0, cost) == [r1, r2]
+    assert (a.in_use, a.fixed, a.reserved["x"], a.lanes["x"]) == (500, 300, 1, 1)
+    assert a.take_lane("x", 300)                 # the reserved lane: nothing more charged
+    assert (a.in_use, a.reserved["x"]) == (500, 0)
+    a.release(100)
+    a.release(100)
+    assert a.admit(1.0, cost) == [r3]            # 300 + 400 + 250 = 950
+    assert (a.in_use, a.fixed, a.peak) == (950, 700, 950)
+    assert not a.take_lane("x", 300)             # a second x lane would pass the budget
+    a.release(250)
+    assert a.take_lane("x", 300) and (a.in_use, a.fixed, a.lanes["x"]) == (1000, 1000, 2)
+    with pytest.raises(AssertionError):
+        a.release(1)                             # lanes are never released
+    # with every byte held by lanes, a new request can never fit: refused at offer
+    with pytest.raises(BinarError) as e:
+        a.offer(R(1, "x"), cost)
+    assert e.value.status == BINAR_ENOMEM
+
+
+def test_request_left_without_room_fails_instead_of_waiting():
+    """A request that fit when offered but not beside lanes charged later
+    (for a class that reached the head of the queue first) fails with
+    BINAR_ENOMEM rather than waiting forever."""
+    class R:
+        def __init__(self, cost, cls):
+            from concurrent.futures import Future
+            self.cost, self.cls, self.future = cost, cls, Future()
+    a = Admission(1000)
+    cost = {"x": 500, "y": 500}.get
+    rx, ry = R(100, "x"), R(450, "y")
+    a.offer(rx, cost)
+    a.offer(ry, cost)                            # 500 + 450 <= 1000 when offered
+    assert a.admit(0.0, cost) == [rx]            # x's lane is now held: 500 + 500 + 450 > 1000
+    a.release(100)
+    assert a.admit(1.0, cost) == []
+    assert not a.waiting
+    with pytest.raises(BinarError) as e:
+        ry.future.result(timeout=1)
+    assert e.value.status == BINAR_ENOMEM
+
+
+def test_lanes_within_budget_end_to_end():
+    """Lane bytes count against the budget: with room for one lane per class
+    plus one request, the server still answers everything, never holds more
+    than the budget, and creates a second lane only when it fits."""
+    reqs = [u32(1000 + 37 * i, i) for i in range(12)] + [u64(500, 99), s16(300, 98)]
+    lane = 1 << 20
+    budget = 3 * lane + request_cost(16, 1400) + request_cost(4, 1500)
+    be = HostBackend(lanes=2, lane_bytes=lane)
+    with Server(budget, backend=be) as srv:
+        res = [f.result(timeout=10) for f in [srv.submit(t) for t in reqs]]
+        assert srv.admission.peak <= budget
+        assert srv.admission.fixed == lane * sum(be.created.values())
+        assert srv.report()["lane_bytes"] == srv.admission.fixed
+    for t, r in zip(reqs, res):
+        k, p = np_stable(t)
+        assert torch.equal(r.keys, k) and torch.equal(r.perm, p)
+
+
+def test_failed_batch_fails_only_its_requests():
+    class Failing(HostBackend):
+        def collect(self, h):
+            if any(k.shape[0] == 13 for k, _ in h):
+                raise BinarError(-4)
+            return h
+    be = Failing(lanes=1)
+    with Server(1 << 30, backend=be, batching=False) as srv:
+        good = srv.submit(u32(12, 1))
+        bad = srv.submit(u32(13, 2))
+        after = srv.submit(u32(14, 3))
+        assert good.result(timeout=10).keys.shape[0] == 12
+        with pytest.raises(BinarError) as e:
+            bad.result(timeout=10)
+        assert e.value.status == -4
+        assert after.result(timeout=10).keys.shape[0] == 14
+        assert srv.report()["failed_batches"] == 1
