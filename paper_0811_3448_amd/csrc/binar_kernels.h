@@ -209,11 +209,13 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *tmp, u
 // counters advance step by step: the ranks follow the input order.  Steps go
 // in groups of G whose operations are issued back to back (masks of all G
 // steps, then all G counter updates, then all G broadcasts), so a group
-// waits for the LDS three times instead of three times per step.  FULL:
-// every key of the tile is valid.
+// waits for the LDS three times instead of three times per step.  UNI: a
+// step whose valid lanes all hold one digit skips the table (its mask is the
+// ballot of the valid lanes; the check costs registers, so only the scatter
+// uses it).  FULL: every key of the tile is valid.
 constexpr int RANK_GROUP = 2;  // steps per group of wave_rank
 
-template <int R, int G, int ITEMS, bool FULL>
+template <int R, int G, int ITEMS, bool FULL, bool UNI = false>
 __device__ __forceinline__ void wave_rank(const uint32_t (&dg)[ITEMS], uint32_t ebase, uint32_t len,
                                           uint32_t *tbl, uint32_t *whist, uint32_t (&rnk)[ITEMS]) {
     if constexpr (R == 2) {
@@ -248,7 +250,17 @@ __device__ __forceinline__ void wave_rank(const uint32_t (&dg)[ITEMS], uint32_t 
             const int j = j0 + g;
             valid[g] = (j < ITEMS) && (FULL || ebase + (uint32_t)j * WAVE < len);
             m[g] = 0ull;
-            if (valid[g]) {
+            // a step whose valid lanes all hold one digit (equal keys, long
+            // runs in skewed data) has the ballot of its valid lanes as the
+            // mask: no table round trip, and no 64 lanes on one LDS word
+            bool uniform = false;
+            if constexpr (UNI) {
+                const unsigned long long vm = __ballot(valid[g]);
+                const uint32_t d0 = __builtin_amdgcn_readlane(dg[j < ITEMS ? j : 0], vm ? __builtin_ctzll(vm) : 0);
+                uniform = __ballot(valid[g] && dg[j < ITEMS ? j : 0] != d0) == 0ull;
+                if (uniform) m[g] = valid[g] ? vm : 0ull;
+            }
+            if (!uniform && valid[g]) {
                 atomicOr(&tbl[2u * dg[j] + half], me);
                 m[g] = *reinterpret_cast<const mask_t *>(&tbl[2u * dg[j]]);
                 tbl[2u * dg[j] + half] = 0u;
@@ -588,6 +600,45 @@ __global__ __launch_bounds__(BT) void k_hist(Work w, int L, int pass) {
                 atomicAdd(&s_h[wv][d], 1u);
             }
         };
+        // Skewed or sorted data (duplicates, low-entropy bits, runs) puts
+        // many lanes of a wave step on one digit, and 64 lanes adding to one
+        // LDS word are served one after another.  So up to PEELS bins of a
+        // step are taken out whole: the first remaining lane's bin (its digit,
+        // or its digit pair with PAIRS), counted with a ballot and added once;
+        // the lanes left after that add one each.  Random keys gain nothing
+        // from it and would pay for the ballots at every step, so a wave
+        // stops peeling in this piece after MISSES steps in a row in which
+        // peeling took out fewer than 16 lanes.
+        constexpr int PEELS = 2;
+        constexpr int MISSES = 4;
+        int misses = (K == 1) ? MISSES : 0;
+        auto count_peeled = [&](const V &v) {
+            const uint32_t d = KT::digit(v, bitpos, wbits);
+            const uint32_t bin = PAIRS ? d * R + (nbits2 > 0 ? KT::digit(v, bitpos + wbits, nbits2) : 0u) : d;
+            const uint64_t all = __ballot(true);
+            uint64_t rest = all;
+#pragma unroll
+            for (int it = 0; it < PEELS; ++it) {
+                if (rest == 0ull) break;
+                const int l0 = __builtin_ctzll(rest);
+                const uint32_t b0 = __builtin_amdgcn_readlane(bin, l0);
+                const uint64_t m = __ballot(bin == b0) & rest;
+                if (lane == l0) {
+                    const uint32_t c = (uint32_t)__popcll(m);
+                    if constexpr (PAIRS) {
+                        const uint32_t sh = (b0 & 1u) * 16u;
+                        const uint32_t old = atomicAdd(&s_p[b0 >> 1], c << sh);
+                        pair_full |= ((old >> sh) & 0xFFFFu) + c > 0xFFFFu;
+                        atomicAdd(&s_h[wv][b0 / R], c);
+                    } else {
+                        atomicAdd(&s_h[wv][b0], c);
+                    }
+                }
+                rest &= ~m;
+            }
+            if ((rest >> lane) & 1ull) count(v);
+            misses = (__popcll(all) - __popcll(rest) < 16) ? misses + 1 : 0;
+        };
         // head and tail one key at a time, the 16-byte aligned body 16 bytes at
         // a time (keys are at least key-size aligned, so `mis` is whole keys)
         const size_t mis = ((16u - (reinterpret_cast<uintptr_t>(src) & 15u)) & 15u) / KB;
@@ -633,9 +684,15 @@ __global__ __launch_bounds__(BT) void k_hist(Work w, int L, int pass) {
                     if (x > seg.begin) desc |= key_after<KB>(prev, v[u][0], km, full);
 #pragma unroll
                     for (int q = 1; q < VN; ++q) desc |= key_after<KB>(v[u][q - 1], v[u][q], km, full);
+                    if (misses < MISSES) {
+#pragma unroll
+                        for (int q = 0; q < VN; ++q) count_peeled(v[u][q]);
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < VN; ++q) count(v[u][q]);
+                    }
 #pragma unroll
                     for (int q = 0; q < VN; ++q) {
-                        count(v[u][q]);
                         a = KT::vand(a, v[u][q]);
                         o = KT::vor(o, v[u][q]);
                     }
@@ -1107,7 +1164,7 @@ __device__ __forceinline__ void scatter_tile(const Work &w, int L, ScatterLds<KB
     }
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) dg[j] = KT::digit(key[j], bitpos, wbits);
-    wave_rank<R, RANK_GROUP, ITEMS, FULL>(dg, ebase, tlen, &S.tbl[wv][0], &S.wh[wv][0], rnk);
+    wave_rank<R, RANK_GROUP, ITEMS, FULL, true>(dg, ebase, tlen, &S.tbl[wv][0], &S.wh[wv][0], rnk);
     __syncthreads();
     // per digit: staged offset of each wave's keys, tile count, global offset
     uint32_t tcnt = 0;
