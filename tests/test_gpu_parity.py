@@ -192,3 +192,67 @@ def test_tied_runs_after_leading_bits(runlen):
     rk, rp = oracle.sort_segmented(k32, off, iota(n))
     assert np.array_equal(gk, rk)
     assert np.array_equal(gp, rp)
+
+
+def mixed_runs(n, seed, kb=4):
+    """Runs of equal keys (whole waves on one digit), runs drawn from two or
+    three values (waves with a few digits), and stretches of random keys, in
+    random order and lengths: the digit count's wave-step peeling switches
+    on and off inside one segment, and its miss counter restarts."""
+    rng = np.random.default_rng(seed)
+    top = (1 << 32) if kb == 4 else (1 << 64)
+    dt = np.uint32 if kb == 4 else np.uint64
+    parts, left = [], n
+    while left > 0:
+        ln = int(min(left, rng.integers(1, 3000)))
+        kind = rng.integers(0, 3)
+        if kind == 0:
+            part = np.full(ln, rng.integers(0, top, dtype=np.uint64), dtype=np.uint64)
+        elif kind == 1:
+            vals = rng.integers(0, top, int(rng.integers(2, 4)), dtype=np.uint64)
+            part = vals[rng.integers(0, vals.shape[0], ln)]
+        else:
+            part = rng.integers(0, top, ln, dtype=np.uint64)
+        parts.append(part.astype(dt))
+        left -= ln
+    return np.concatenate(parts)
+
+
+@pytest.mark.parametrize("kb", [4, 8])
+@pytest.mark.parametrize("k,tile,T", [(8, 8192, 5120), (8, 4096, 64), (4, 2048, 300)])
+def test_mixed_runs(kb, k, tile, T):
+    if kb == 8 and tile == 8192:
+        tile = 4096         # the 8192-key tile is built for 4-byte keys only
+    compare(mixed_runs(200_003, 40 + kb + k, kb), params=P(k, tile, T, 1))
+
+
+@pytest.mark.parametrize("kb", [4, 8])
+def test_sorted_runs_first_pass_pairs(kb):
+    """2^26 keys in long sorted runs: the first pass of one large array counts
+    digit pairs, and its waves hold one pair bin for long stretches (peeled
+    pairs, bins that pass 65535 inside a block); the result is checked on
+    the device completely and at sampled oracle ranks."""
+    import torch
+    import paper_0811_3448_amd as binar
+    from oracle.definition import stable_rank_u
+    from test_gpu_fullsize import device_checks
+    n = 1 << 26
+    base = workloads.u32_uniform(n, 4242) if kb == 4 else workloads.u64_uniform(n, 4243)
+    keys = base.copy()
+    runs = 64
+    for r in range(runs):       # sorted runs of n / 64 keys each
+        lo, hi = r * (n // runs), (r + 1) * (n // runs)
+        keys[lo:hi] = np.sort(base[lo:hi])
+    print("sorted runs kb=%d n=%d" % (kb, n), flush=True)
+    kin = torch.from_numpy(keys.view(np.int32 if kb == 4 else np.int64)).cuda()
+    kd = kin.clone()
+    pd = torch.arange(n, dtype=torch.int32, device="cuda")
+    binar.sort(kd, pd, params=P(8, 8192 if kb == 4 else 4096, 5120, 1))
+    torch.cuda.synchronize()
+    assert binar.stats()["status"] == 0
+    device_checks(kin, kd, pd, kb)
+    gk = kd.cpu().numpy().view(keys.dtype)
+    gp = pd.cpu().numpy().view(np.uint32)
+    for i in workloads.below(12, 4244 + kb, n).astype(np.int64).tolist() + [0, n - 1]:
+        r = stable_rank_u(keys, i)
+        assert gp[r] == i and gk[r] == keys[i], i
