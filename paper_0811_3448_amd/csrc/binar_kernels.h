@@ -1700,22 +1700,25 @@ __device__ __forceinline__ typename KeyT<KB>::V unfield16(typename KeyT<KB>::V b
 // [s, s + 16) (MSB-first): each key travels as one 32-bit word, (those 16
 // bits << 16) | its index in the sub-array, so that a pass moves 4 bytes per
 // key whatever the key width, and the payload stays where it was loaded.
-// Windows of up to 8 bits from lb down to fb.  On return the words in sorted
-// order are in S.keys, read as 32-bit words (word i = the i-th key).
-template <int KB, int BT, int ITEMS, bool PAY>
+// Windows of up to 8 bits from lb down to fb.  The caller passes the
+// words of its keys (key e of the sub-array at (wave, step, lane) = e); on
+// return the words in sorted order are in S.keys, read as 32-bit words
+// (word i = the i-th key).
+template <int KB, int BT, int ITEMS, bool PAY, class F>
 __device__ __forceinline__ void packed_passes(FinishLds<KB, BT, ITEMS, PAY> &S, Canon diff, int fb, int lb, int s,
-                                              uint32_t ebase, uint32_t we) {
+                                              uint32_t ebase, uint32_t we, F &&key_at) {
     typedef uint32_t __attribute__((may_alias)) word_t;
     word_t *pk = reinterpret_cast<word_t *>(&S.keys[0]);
     constexpr int R = 256;
     const int wv = threadIdx.x / WAVE, lane = lane_id();
     uint32_t pw[ITEMS];
-    // the words, from the keys in input order (every read comes before the
-    // barriers of the first window, every write after them)
+    // the words (key_at(j) = key e = ebase + 64 j, from registers or from the
+    // keys in LDS in input order: every read comes before the barriers of
+    // the first window, every write after them)
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
         const uint32_t e = ebase + j * WAVE;
-        pw[j] = (e < we) ? (field16<KB>(S.keys[e], s) << 16) | e : 0u;
+        pw[j] = (e < we) ? (field16<KB>(key_at(j), s) << 16) | e : 0u;
     }
     int hib = lb;
     bool first = true;
@@ -1885,12 +1888,20 @@ __device__ bool fix_runs(FinishLds<KB, BT, ITEMS, PAY> &S, int pe, uint32_t len,
         if (!canon_eq_under(KT::canon(S.keys[p + 1]), k, pm)) return false;
         return p == 0 || !canon_eq_under(KT::canon(S.keys[p - 1]), k, pm);
     };
-    uint32_t cnt = 0;
-    for (uint32_t p = threadIdx.x; p < len; p += BT) cnt += is_start(p) ? 1u : 0u;
+    // each thread tests its keys once and keeps the answers as bits (at most
+    // ITEMS keys a thread)
+    static_assert(ITEMS <= 32, "run-start bits must fit one word");
+    uint32_t cnt = 0, starts = 0;
+    for (uint32_t p = threadIdx.x, i = 0; p < len; p += BT, ++i)
+        if (is_start(p)) {
+            ++cnt;
+            starts |= 1u << i;
+        }
     uint32_t nruns;
     uint32_t at = block_excl_scan<BT>(cnt, S.tmp, &nruns);  // every thread: it holds barriers
-    for (uint32_t p = threadIdx.x; p < len; p += BT)
-        if (is_start(p)) list[at++] = (uint16_t)p;
+    if (nruns == 0u) return false;                         // no tied run: nothing to order
+    for (uint32_t p = threadIdx.x, i = 0; p < len; p += BT, ++i)
+        if ((starts >> i) & 1u) list[at++] = (uint16_t)p;
     __syncthreads();
     const Canon km = canon_lead_mask(nb);
     for (uint32_t r0 = (uint32_t)wv * WAVE; r0 < nruns; r0 += NW * WAVE) {
@@ -1975,9 +1986,36 @@ void k_finish(Work w, int cls) {
             if (threadIdx.x == 0) atomicOr(&ctl->error, ERR_INTERNAL);
             continue;
         }
-        // load into LDS in input order, AND/OR on the way
+        // each wave's share of the keys (wave_share): 4-byte keys with a
+        // payload are loaded in that order into registers, one per lane and
+        // step, so that the first LDS pass can rank them from there; other
+        // keys go to LDS in input order with 16-byte vectors (keys-only
+        // classes run more waves per SIMD and have no registers to spare).
+        // AND/OR on the way.
+        constexpr bool REGK = KB == 4 && PAY;
+        uint32_t wb = 0u, we = 0u;
+        if constexpr (REGK) wave_share<BT, ITEMS>(len, wv, wb, we);
         V a = KT::ones(), o = KT::zero();
-        fin_load_keys<KB, NVK, BT>(w.keys[parity], fe.begin, (size_t)fe.begin + len, S.keys, a, o, w.kind);
+        V kr[REGK ? ITEMS : 1];
+        if constexpr (REGK) {
+            const uint32_t ebase = wb + (uint32_t)lane;
+            // every load is valid (indices clamped into the sub-array), the
+            // lanes past the wave's share drop theirs
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) {
+                const uint32_t e = ebase + j * WAVE;
+                kr[j] = ld_key<KB>(w.keys[parity], (size_t)fe.begin + min(e, len - 1u), w.kind);
+            }
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) {
+                if (ebase + j * WAVE < we) {
+                    a = KT::vand(a, kr[j]);
+                    o = KT::vor(o, kr[j]);
+                }
+            }
+        } else {
+            fin_load_keys<KB, NVK, BT>(w.keys[parity], fe.begin, (size_t)fe.begin + len, S.keys, a, o, w.kind);
+        }
         if constexpr (PAY) fin_load_pay<NVP, BT>(w.pay[parity], fe.begin, (size_t)fe.begin + len, S.pay);
         Canon ca = KT::canon(a), co = KT::canon(o);
 #pragma unroll
@@ -2014,8 +2052,7 @@ void k_finish(Work w, int cls) {
             __syncthreads();
             continue;
         }
-        uint32_t wb, we;
-        wave_share<BT, ITEMS>(len, wv, wb, we);
+        if constexpr (!REGK) wave_share<BT, ITEMS>(len, wv, wb, we);
         const uint32_t ebase = wb + (uint32_t)lane;
         const int fb = first_set_from(diff, bitpos, NB);
         if constexpr (KB != 16) {
@@ -2024,7 +2061,11 @@ void k_finish(Work w, int cls) {
             const int s = min(fb, 8 * KB - 16);
             const uint64_t fmask = (0xFFFFull << 48) >> s;  // the field in the left-aligned word
             if (lb >= bitpos && lb - s <= 15 && ((diff.hi & ~fmask) | diff.lo) == 0ull) {
-                packed_passes<KB, BT, ITEMS, PAY>(S, diff, fb, lb, s, ebase, we);
+                // the keys in registers (REGK) or in LDS in input order
+                packed_passes<KB, BT, ITEMS, PAY>(S, diff, fb, lb, s, ebase, we, [&](int j) -> V {
+                    if constexpr (REGK) return kr[j];
+                    else return S.keys[ebase + j * WAVE];
+                });
                 typedef uint32_t __attribute__((may_alias)) word_t;
                 const V base = (KB == 4) ? (V)(ah >> 32) : (V)ah;
                 fin_store_packed<KB, BT, PAY>(w, fe.begin, (size_t)fe.begin + len,
@@ -2032,6 +2073,15 @@ void k_finish(Work w, int cls) {
                 __syncthreads();
                 continue;
             }
+        }
+        if constexpr (REGK) {
+            // every other path works on the keys in LDS, input order
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) {
+                const uint32_t e = ebase + j * WAVE;
+                if (e < we) S.keys[e] = kr[j];
+            }
+            __syncthreads();
         }
         if (lb >= bitpos) {
             // sort by the two leading 8-bit windows that start at varying bits;
