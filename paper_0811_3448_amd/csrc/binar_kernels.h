@@ -1636,25 +1636,24 @@ __device__ __forceinline__ void fin_offsets(L &S) {
 // index in [bitpos, end] (MSB-first indices), least significant window of up
 // to 8 bits first; constant windows are skipped.  The order lives in S
 // between passes.  Each wave ranks its share [ebase - lane, we)
-// (wave_share).
-template <int KB, int BT, int ITEMS, bool PAY>
+// (wave_share).  REGFIRST: the first window takes key e = ebase + 64 j from
+// key_at(j) (registers) instead of the keys in LDS in input order.
+template <int KB, int BT, int ITEMS, bool PAY, bool REGFIRST, class F>
 __device__ __forceinline__ void lds_passes(FinishLds<KB, BT, ITEMS, PAY> &S, Canon diff, int bitpos, int end,
-                                           uint32_t ebase, uint32_t we) {
+                                           uint32_t ebase, uint32_t we, F &&key_at) {
     using KT = KeyT<KB>;
     using V = typename KT::V;
     constexpr int KL = 8;
     constexpr int R = 1 << KL;
     const int wv = threadIdx.x / WAVE, lane = lane_id();
-    int hib = last_set_below(diff, bitpos, end + 1);
-    while (hib >= bitpos) {
-        const int lo = max(bitpos, hib - KL + 1);
-        const int wbits = hib - lo + 1;
+    // one window [lo, lo + wbits) over keys key_of(j)
+    auto window = [&](int lo, int wbits, auto &&key_of) {
         V key[ITEMS];
         uint32_t dg[ITEMS], rnk[ITEMS];
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
             const uint32_t e = ebase + j * WAVE;
-            key[j] = (e < we) ? S.keys[e] : KT::zero();
+            key[j] = (e < we) ? key_of(j) : KT::zero();
             dg[j] = KT::digit(key[j], lo, wbits);
         }
         wave_rank<R, RANK_GROUP, ITEMS, false>(dg, ebase, we, &S.tbl[wv][0], &S.wh[wv][0], rnk);
@@ -1678,6 +1677,18 @@ __device__ __forceinline__ void lds_passes(FinishLds<KB, BT, ITEMS, PAY> &S, Can
         // each wave clears its own counters: only it touches them before
         // the next barrier
         for (int i = lane; i < R; i += WAVE) S.wh[wv][i] = 0u;
+    };
+    int hib = last_set_below(diff, bitpos, end + 1);
+    if constexpr (REGFIRST) {
+        if (hib < bitpos) return;
+        const int lo = max(bitpos, hib - KL + 1);
+        window(lo, hib - lo + 1, key_at);
+        hib = last_set_below(diff, bitpos, lo);
+    }
+    auto in_lds = [&](int j) -> V { return S.keys[ebase + j * WAVE]; };
+    while (hib >= bitpos) {
+        const int lo = max(bitpos, hib - KL + 1);
+        window(lo, hib - lo + 1, in_lds);
         hib = last_set_below(diff, bitpos, lo);
     }
 }
@@ -2074,8 +2085,11 @@ void k_finish(Work w, int cls) {
                 continue;
             }
         }
-        if constexpr (REGK) {
-            // every other path works on the keys in LDS, input order
+        // the first window ranks the keys in registers where the class has
+        // registers to spare for it (at most 12 keys a thread); otherwise
+        // they go to LDS in input order first
+        constexpr bool REGW = REGK && ITEMS <= 12;
+        if constexpr (REGK && !REGW) {
 #pragma unroll
             for (int j = 0; j < ITEMS; ++j) {
                 const uint32_t e = ebase + j * WAVE;
@@ -2083,15 +2097,27 @@ void k_finish(Work w, int cls) {
             }
             __syncthreads();
         }
+        auto in_lds = [&](int j) -> V { return S.keys[ebase + j * WAVE]; };
         if (lb >= bitpos) {
             // sort by the two leading 8-bit windows that start at varying bits;
             // keys still tied on them are ordered by fix_runs, or, if a tied
             // run is long, by passes over every varying bit
             const int f2 = first_set_from(diff, min(fb + 8, NB), NB);
             const int pe = (f2 >= NB) ? lb : min(lb, f2 + 7);
-            lds_passes<KB, BT, ITEMS, PAY>(S, diff, bitpos, pe, ebase, we);
+            lds_passes<KB, BT, ITEMS, PAY, REGW>(S, diff, bitpos, pe, ebase, we, [&](int j) -> V {
+                if constexpr (REGW) return kr[j];
+                else return in_lds(j);
+            });
             if (pe < lb && fix_runs<KB, BT, ITEMS, PAY>(S, pe, len, NB))
-                lds_passes<KB, BT, ITEMS, PAY>(S, diff, bitpos, lb, ebase, we);
+                lds_passes<KB, BT, ITEMS, PAY, false>(S, diff, bitpos, lb, ebase, we, in_lds);
+        } else if constexpr (REGW) {
+            // nothing varies (the keys sit in B): written out as they are
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) {
+                const uint32_t e = ebase + j * WAVE;
+                if (e < we) S.keys[e] = kr[j];
+            }
+            __syncthreads();
         }
         fin_store_keys<KB, BT>(w.keys[0], fe.begin, (size_t)fe.begin + len, S.keys, w.kind);
         if constexpr (PAY) fin_store_pay<BT>(w.pay[0], fe.begin, (size_t)fe.begin + len, S.pay);
