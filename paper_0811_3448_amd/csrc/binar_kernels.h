@@ -519,7 +519,8 @@ __device__ __forceinline__ typename KeyT<KB>::V raw_key(typename KeyT<KB>::V v, 
 // PAIRS (first pass of one array): the digit of the next K bits is counted
 // too, per pair (this digit, next digit), in 16-bit LDS bins packed two to a
 // word; each block leaves its pair counts in its row of w.pair_part (and
-// k_pair_sum adds the rows).  A bin that would pass 65535 sets
+// k_pair_sum adds the rows).  A block that holds more than 65535 keys of
+// one digit (so that one of its pair bins could pass 65535) sets
 // ctl->fuse_bad: the pair counts are then not used (the piece counts come
 // from the exact per-wave counts either way).
 // A pass whose counts came with pass 0's (ctl->fused_pass) reads no key.
@@ -557,7 +558,10 @@ __global__ __launch_bounds__(BT) void k_hist(Work w, int L, int pass) {
     if (LOOKBACK)
         for (size_t i = (size_t)t0 * R + threadIdx.x; i < (size_t)t1 * R; i += BT) w.status[i] = 0u;
     __syncthreads();
-    bool pair_full = false;  // a pair bin of this thread's reached 65535
+    // a pair bin can pass 65535 (and spill into its neighbour) only if its
+    // digit has more than 65535 keys in the block: checked on the block's
+    // digit totals when they are flushed, so the pair adds need no result
+    bool pair_full = false;
 
     uint32_t slot = find_slot(w.list[L], nslots, t0);
     for (uint32_t t = t0; t < t1;) {
@@ -587,8 +591,7 @@ __global__ __launch_bounds__(BT) void k_hist(Work w, int L, int pass) {
             if constexpr (PAIRS) {
                 const uint32_t b = d * R + (nbits2 > 0 ? KT::digit(v, bitpos + wbits, nbits2) : 0u);
                 const uint32_t sh = (b & 1u) * 16u;
-                const uint32_t old = atomicAdd(&s_p[b >> 1], 1u << sh);
-                pair_full |= ((old >> sh) & 0xFFFFu) == 0xFFFFu;
+                atomicAdd(&s_p[b >> 1], 1u << sh);
             }
             if constexpr (K == 1) {
                 const uint64_t act = __ballot(true), ones = __ballot(d != 0u);
@@ -627,8 +630,7 @@ __global__ __launch_bounds__(BT) void k_hist(Work w, int L, int pass) {
                     const uint32_t c = (uint32_t)__popcll(m);
                     if constexpr (PAIRS) {
                         const uint32_t sh = (b0 & 1u) * 16u;
-                        const uint32_t old = atomicAdd(&s_p[b0 >> 1], c << sh);
-                        pair_full |= ((old >> sh) & 0xFFFFu) + c > 0xFFFFu;
+                        atomicAdd(&s_p[b0 >> 1], c << sh);
                         atomicAdd(&s_h[wv][b0 / R], c);
                     } else {
                         atomicAdd(&s_h[wv][b0], c);
@@ -724,6 +726,7 @@ __global__ __launch_bounds__(BT) void k_hist(Work w, int L, int pass) {
                 s_h[q][d] = 0u;
             }
             row[d] = c;
+            if (PAIRS) pair_full |= c > 0xFFFFu;
         }
         if constexpr (PAIRS) {
             // one piece per block (one array): the pairs go to the block's

@@ -2,9 +2,10 @@
 counts (one array of at least 2^26 keys): the counters show that the second
 pass read no key, and the result is checked completely on the device
 (nondecreasing, payload a permutation, keys follow it, ties in input order)
-and at sampled inputs against the oracle's stable rank.  An input whose pair
-bins overflow 16 bits within one block falls back to counting the second
-pass's digits from the keys, with the same checks."""
+and at sampled inputs against the oracle's stable rank.  An input whose
+blocks hold more than 65535 keys of one leading digit (so that a 16-bit
+pair bin could overflow) falls back to counting the second pass's digits
+from the keys, with the same checks."""
 import numpy as np
 import pytest
 
@@ -58,7 +59,8 @@ def test_second_pass_counts_from_pairs(kb):
 def test_pair_bins_overflow_falls_back():
     """Each block's chunk holds one leading byte and two second bytes (0 and
     128), so a pair bin passes 65535 in every block; bit 8 varies and the
-    256 children are even, so only the overflow stops the pair counts."""
+    256 children are even, so only the overflow guard stops the pair
+    counts."""
     from paper_0811_3448_amd import Params
     i = np.arange(N, dtype=np.uint64)
     rnd = workloads.u32_uniform(N, 7003)
