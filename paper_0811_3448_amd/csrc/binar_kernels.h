@@ -209,15 +209,19 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *tmp, u
 // counters advance step by step: the ranks follow the input order.  Steps go
 // in groups of G whose operations are issued back to back (masks of all G
 // steps, then all G counter updates, then all G broadcasts), so a group
-// waits for the LDS three times instead of three times per step.  UNI: a
-// step whose valid lanes all hold one digit skips the table (its mask is the
-// ballot of the valid lanes; the check costs registers, so only the scatter
-// uses it).  FULL: every key of the tile is valid.
+// waits for the LDS three times instead of three times per step.  UNI: up
+// to two digits of a step bypass the table (below; the check costs
+// registers, so only the scatter uses it).  FULL: every key of the tile is
+// valid.
 constexpr int RANK_GROUP = 2;  // steps per group of wave_rank
+constexpr int PEEL_MISSES = 4;  // unproductive steps after which a wave stops peeling digits
+constexpr int PEEL_RETRY = 32;  // steps after which a wave that stopped peeling tries again
+constexpr int PEEL_GAIN = 32;   // lanes a step's peeling must take out to count as worth it
 
 template <int R, int G, int ITEMS, bool FULL, bool UNI = false>
 __device__ __forceinline__ void wave_rank(const uint32_t (&dg)[ITEMS], uint32_t ebase, uint32_t len,
-                                          uint32_t *tbl, uint32_t *whist, uint32_t (&rnk)[ITEMS]) {
+                                          uint32_t *tbl, uint32_t *whist, uint32_t (&rnk)[ITEMS],
+                                          int *peel_misses = nullptr) {
     if constexpr (R == 2) {
         // the paper's one-bit step: a ballot of the bit gives each lane the
         // lanes below it with the same bit (mbcnt), its popcount the wave's
@@ -250,17 +254,39 @@ __device__ __forceinline__ void wave_rank(const uint32_t (&dg)[ITEMS], uint32_t 
             const int j = j0 + g;
             valid[g] = (j < ITEMS) && (FULL || ebase + (uint32_t)j * WAVE < len);
             m[g] = 0ull;
-            // a step whose valid lanes all hold one digit (equal keys, long
-            // runs in skewed data) has the ballot of its valid lanes as the
-            // mask: no table round trip, and no 64 lanes on one LDS word
-            bool uniform = false;
+            // skewed data puts many lanes of a step on one digit (and 64
+            // lanes on one LDS word are served one after another).  A step
+            // whose valid lanes all hold one digit takes the ballot of its
+            // valid lanes as the mask.  In other steps up to two digits are
+            // taken out whole (the first remaining lane's digit each time,
+            // their masks the ballot of their lanes) and the other lanes go
+            // through the table; a wave stops that after PEEL_MISSES mixed
+            // steps in a row in which it took out fewer than PEEL_GAIN lanes,
+            // and tries again every PEEL_RETRY mixed steps (*peel_misses,
+            // kept by the caller across tiles).
+            bool peeled = false;
             if constexpr (UNI) {
+                const uint32_t dj = dg[j < ITEMS ? j : 0];
                 const unsigned long long vm = __ballot(valid[g]);
-                const uint32_t d0 = __builtin_amdgcn_readlane(dg[j < ITEMS ? j : 0], vm ? __builtin_ctzll(vm) : 0);
-                uniform = __ballot(valid[g] && dg[j < ITEMS ? j : 0] != d0) == 0ull;
-                if (uniform) m[g] = valid[g] ? vm : 0ull;
+                const uint32_t d0 = __builtin_amdgcn_readlane(dj, vm ? __builtin_ctzll(vm) : 0);
+                const unsigned long long p0 = __ballot(valid[g] && dj == d0);
+                if (p0 == vm) {
+                    m[g] = valid[g] ? vm : 0ull;
+                    peeled = true;
+                } else {
+                    if (*peel_misses >= PEEL_MISSES && ++*peel_misses >= PEEL_MISSES + PEEL_RETRY)
+                        *peel_misses = PEEL_MISSES - 1;
+                    if (*peel_misses < PEEL_MISSES) {
+                        const unsigned long long rest = vm & ~p0;
+                        const uint32_t d1 = __builtin_amdgcn_readlane(dj, __builtin_ctzll(rest));
+                        const unsigned long long p1 = __ballot(valid[g] && dj == d1) & rest;
+                        peeled = valid[g] && (dj == d0 || dj == d1);
+                        if (peeled) m[g] = (dj == d0) ? p0 : p1;
+                        *peel_misses = (__popcll(p0) + __popcll(p1) < PEEL_GAIN) ? *peel_misses + 1 : 0;
+                    }
+                }
             }
-            if (!uniform && valid[g]) {
+            if (!peeled && valid[g]) {
                 atomicOr(&tbl[2u * dg[j] + half], me);
                 m[g] = *reinterpret_cast<const mask_t *>(&tbl[2u * dg[j]]);
                 tbl[2u * dg[j] + half] = 0u;
@@ -1141,7 +1167,8 @@ __device__ __forceinline__ void load_tile(const Work &w, const SegEntry &seg, ui
 template <int KB, int K, int BT, int ITEMS, bool PAY, bool LOOKBACK, bool FULL>
 __device__ __forceinline__ void scatter_tile(const Work &w, int L, ScatterLds<KB, K, BT, ITEMS, PAY, LOOKBACK> &S,
                                              const SegEntry &seg, uint32_t t, uint32_t slot,
-                                             typename KeyT<KB>::V (&key)[ITEMS], const uint32_t (&pay)[ITEMS]) {
+                                             typename KeyT<KB>::V (&key)[ITEMS], const uint32_t (&pay)[ITEMS],
+                                             int &peel_misses) {
     using KT = KeyT<KB>;
     using V = typename KT::V;
     constexpr int R = 1 << K;
@@ -1167,7 +1194,7 @@ __device__ __forceinline__ void scatter_tile(const Work &w, int L, ScatterLds<KB
     }
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) dg[j] = KT::digit(key[j], bitpos, wbits);
-    wave_rank<R, RANK_GROUP, ITEMS, FULL, true>(dg, ebase, tlen, &S.tbl[wv][0], &S.wh[wv][0], rnk);
+    wave_rank<R, RANK_GROUP, ITEMS, FULL, true>(dg, ebase, tlen, &S.tbl[wv][0], &S.wh[wv][0], rnk, &peel_misses);
     __syncthreads();
     // per digit: staged offset of each wave's keys, tile count, global offset
     uint32_t tcnt = 0;
@@ -1349,6 +1376,7 @@ __global__ __launch_bounds__(BT) void k_scatter(Work w, int L, int pass) {
 
     V key[ITEMS];
     uint32_t pay[ITEMS];
+    int peel_misses = 0;  // the ranking's digit peeling (see wave_rank)
     if constexpr (LOOKBACK) {
         // tiles in ticket order; each looks back over its segment's earlier tiles
         for (;;) {
@@ -1366,9 +1394,9 @@ __global__ __launch_bounds__(BT) void k_scatter(Work w, int L, int pass) {
             if ((seg.info >> 16) & SEG_SKIP) continue;
             load_tile<KB, BT, ITEMS, PAY>(w, seg, t, key, pay);
             if (seg.len - (t - seg.tile_start) * TILE >= TILE)
-                scatter_tile<KB, K, BT, ITEMS, PAY, true, true>(w, L, S, seg, t, slot, key, pay);
+                scatter_tile<KB, K, BT, ITEMS, PAY, true, true>(w, L, S, seg, t, slot, key, pay, peel_misses);
             else
-                scatter_tile<KB, K, BT, ITEMS, PAY, true, false>(w, L, S, seg, t, slot, key, pay);
+                scatter_tile<KB, K, BT, ITEMS, PAY, true, false>(w, L, S, seg, t, slot, key, pay, peel_misses);
         }
     } else {
     // chunked: walk tiles t0 .. t1 in order; the next tile of the same segment
@@ -1403,9 +1431,9 @@ __global__ __launch_bounds__(BT) void k_scatter(Work w, int L, int pass) {
         const bool pref = tn < t1 && tn < seg_end;
         if (pref) load_tile<KB, BT, ITEMS, PAY>(w, seg, tn, keyn, payn);
         if (seg.len - (t - seg.tile_start) * TILE >= TILE)
-            scatter_tile<KB, K, BT, ITEMS, PAY, false, true>(w, L, S, seg, t, slot, key, pay);
+            scatter_tile<KB, K, BT, ITEMS, PAY, false, true>(w, L, S, seg, t, slot, key, pay, peel_misses);
         else
-            scatter_tile<KB, K, BT, ITEMS, PAY, false, false>(w, L, S, seg, t, slot, key, pay);
+            scatter_tile<KB, K, BT, ITEMS, PAY, false, false>(w, L, S, seg, t, slot, key, pay, peel_misses);
         t = tn;
         if (pref) {
 #pragma unroll
