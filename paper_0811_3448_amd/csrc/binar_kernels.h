@@ -1092,7 +1092,7 @@ __global__ __launch_bounds__(THREADS) void k_copyback(Work w) {
 // step, so the (wave, step, lane) order is the input order and a stable rank
 // is: keys of the digit in earlier waves + the rank inside the wave.
 //
-// Bucket offsets of a tile (s_gofs[d] = global index of staged position 0
+// Bucket offsets of a tile (gw[d].x = global index of staged position 0
 // of digit d):
 //   LOOKBACK = false: the block owns the same chunk of tiles as in k_hist and
 //     walks it in order, starting each piece from bases + piece prefix and
@@ -1119,9 +1119,11 @@ struct ScatterLds {
     uint32_t pay[PAY ? TILE : 1];
     alignas(8) uint32_t tbl[NW][2 * R];  // lane masks of the wave ranking
     uint32_t wh[NW][R];             // per-wave digit counts -> staged offset of (wave, digit)
-    uint32_t gofs[R];               // global index of staged position 0 of digit d
+    // per digit d: .x = global index of staged position 0, .y = staged keys
+    // below this global index are written now (chunked scatter only): one
+    // 8-byte read gives the write-out both
+    uint2 gw[R];
     uint32_t run[R];                // chunked offsets: next global index of digit d in this piece
-    uint32_t wlim[CR];              // staged keys below this global index are written now
     uint32_t cc[CR];                // carried keys of digit d (global [run - cc, run))
     uint32_t ccw[CR];               // carried keys written this tile, from global index clo
     uint32_t clo[CR];
@@ -1239,7 +1241,7 @@ __device__ __forceinline__ void scatter_tile(const Work &w, int L, ScatterLds<KB
                 }
                 st_agent(st, ST_INC | (excl + tcnt));
             }
-            if (tcnt) S.gofs[threadIdx.x] = w.bases[L][(size_t)slot * R + threadIdx.x] + excl - dstart;
+            if (tcnt) S.gw[threadIdx.x].x = w.bases[L][(size_t)slot * R + threadIdx.x] + excl - dstart;
         } else {
             // the run of digit d so far: carried [gpos - cc, gpos) + this tile's
             // [gpos, gpos + tcnt); write everything below the last burst
@@ -1250,8 +1252,7 @@ __device__ __forceinline__ void scatter_tile(const Work &w, int L, ScatterLds<KB
             const uint32_t lo = gpos - cc, hi = gpos + tcnt;
             const uint32_t cut = hi & ~(CB - 1u);
             const uint32_t wlim = cut > lo ? cut : lo;
-            S.gofs[threadIdx.x] = gpos - dstart;
-            S.wlim[threadIdx.x] = wlim;
+            S.gw[threadIdx.x] = make_uint2(gpos - dstart, wlim);
             S.ccw[threadIdx.x] = cut > lo ? cc : 0u;
             S.clo[threadIdx.x] = lo;
             S.cc[threadIdx.x] = hi - wlim;
@@ -1295,11 +1296,12 @@ __device__ __forceinline__ void scatter_tile(const Work &w, int L, ScatterLds<KB
         if (FULL || p < tlen) {
             const V k = S.keys[p];
             const uint32_t d = KT::digit(k, bitpos, wbits);
-            const uint32_t g = S.gofs[d] + p;
-            if (!LOOKBACK && g >= S.wlim[d]) {
+            const uint2 gw = S.gw[d];
+            const uint32_t g = gw.x + p;
+            if (!LOOKBACK && g >= gw.y) {
                 // does not fill a burst yet: carry it to the next tile
-                S.ckeys[d][g - S.wlim[d]] = k;
-                if (PAY) S.cpay[d][g - S.wlim[d]] = S.pay[p];
+                S.ckeys[d][g - gw.y] = k;
+                if (PAY) S.cpay[d][g - gw.y] = S.pay[p];
             } else if (g < w.n_total) {
                 // whole bursts from this tile: streaming stores (the partial
                 // bursts completed from the carry above stay ordinary, so the
