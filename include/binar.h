@@ -71,8 +71,9 @@ extern "C" {
  *   digit_bits : bits taken per global pass: 1, 4, 5, 6, 7 or 8 (1 = the
  *                paper's binary partition step, made stable).
  *   tile_keys  : keys per scatter tile: 4096 for every digit_bits; 2048 for
- *                digit_bits 1, 4 and 8; 8192 for 4-byte keys with digit_bits 8.
- *                Other pairs return BINAR_EINVAL.
+ *                digit_bits 1, 4 and 8; 8192 for 4-byte keys with digit_bits 8;
+ *                6144 for 8-byte keys with digit_bits 8.  Other pairs return
+ *                BINAR_EINVAL.
  *   finish_max : largest sub-array finished in on-chip memory (LDS) by one
  *                workgroup; capped by the key width's largest LDS class.
  *   offsets    : how a scatter tile finds where its keys go:

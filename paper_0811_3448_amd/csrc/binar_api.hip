@@ -58,7 +58,7 @@ bool valid_kb(uint32_t kb) { return kb == 4 || kb == 8 || kb == 16; }
 
 bool supported_k(uint32_t k) { return k == 1 || (k >= 4 && k <= 8); }
 
-bool supported_tile(uint32_t t) { return t == 2048 || t == 4096 || t == 8192; }
+bool supported_tile(uint32_t t) { return t == 2048 || t == 4096 || t == 6144 || t == 8192; }
 
 // Effective parameters: the nonzero fields of p over the defaults d, then
 // the built-in choices for what is still zero.
@@ -70,12 +70,13 @@ int resolve_over(uint32_t kb, bool pay, binar_params d, const binar_params *p, R
         if (p->offsets) d.offsets = p->offsets;
     }
     if (!d.digit_bits) d.digit_bits = 8;
-    if (!d.tile_keys) d.tile_keys = (kb == 4 && d.digit_bits == 8) ? 8192 : 4096;
+    if (!d.tile_keys) d.tile_keys = (d.digit_bits != 8) ? 4096 : (kb == 4) ? 8192 : (kb == 8) ? 6144 : 4096;
     if (!d.offsets) d.offsets = 1;
     const uint32_t tmax = fin_cap(kb, NCLASS - 1);
     if (!d.finish_max) d.finish_max = tmax;
     if (!supported_k(d.digit_bits) || !supported_tile(d.tile_keys) || d.offsets > 2) return BINAR_EINVAL;
     if (d.tile_keys == 8192 && (kb != 4 || d.digit_bits != 8)) return BINAR_EINVAL;
+    if (d.tile_keys == 6144 && (kb != 8 || d.digit_bits != 8)) return BINAR_EINVAL;
     if (d.tile_keys == 2048 && d.digit_bits > 4 && d.digit_bits < 8) return BINAR_EINVAL;
     const uint32_t nbits = (p && p->key_bits) ? p->key_bits : 8u * kb;
     if (nbits > 8u * kb) return BINAR_EINVAL;

@@ -84,6 +84,10 @@ struct ScatterShape<4096> {
     static constexpr int BT = 512, ITEMS = 8;
 };
 template <>
+struct ScatterShape<6144> {
+    static constexpr int BT = 768, ITEMS = 8;
+};
+template <>
 struct ScatterShape<8192> {
     static constexpr int BT = 1024, ITEMS = 8;
 };
@@ -311,6 +315,9 @@ int dispatch_k(const Resolved &r, const Work &w, const Layout &L, const uint32_t
                           : enqueue<KB, KK, TT, PAY, false>(w, L, so, ns, n, st);
     if constexpr (KB == 4) {
         BINAR_CASE(8, 8192)  // wider keys: 8192 of them do not fit in LDS
+    }
+    if constexpr (KB == 8) {
+        BINAR_CASE(8, 6144)  // the most 8-byte keys a 1024-thread tile stages in LDS
     }
     BINAR_CASE(8, 4096)
     BINAR_CASE(8, 2048)

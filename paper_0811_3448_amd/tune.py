@@ -5,7 +5,7 @@ array or a batch of segments -- it times every built combination of
 
   * digit width k (1 = the one-bit partition step, 4 .. 8),
   * scatter tile (which fixes the scatter workgroup: 2048 keys -> 256
-    threads, 4096 -> 512, 8192 -> 1024),
+    threads, 4096 -> 512, 6144 -> 768, 8192 -> 1024),
   * LDS-finish threshold T (the largest sub-array one workgroup finishes
     on chip),
   * offset scheme (per-chunk counts, or decoupled look-back),
@@ -34,7 +34,7 @@ DEFAULT_CACHE = os.environ.get("BINAR_TUNE_CACHE", os.path.join(_HERE, "tuned_gf
 FORMAT = 1
 
 DIGIT_BITS = (1, 4, 5, 6, 7, 8)
-TILE_THREADS = {2048: 256, 4096: 512, 8192: 1024}
+TILE_THREADS = {2048: 256, 4096: 512, 6144: 768, 8192: 1024}
 
 
 def bucket(n: int) -> int:

@@ -67,6 +67,11 @@ def test_bad_tuning_knobs(lib):
     for k in (5, 6, 7):
         assert binar.workspace_bytes(4, 1000, True, params=binar.Params(digit_bits=k, tile_keys=2048)) == 0
         assert binar.workspace_bytes(4, 1000, True, params=binar.Params(digit_bits=k, tile_keys=8192)) == 0
+    # the 6144-key tile: 8-byte keys with 8-bit digits only
+    assert binar.workspace_bytes(8, 1000, True, params=binar.Params(digit_bits=8, tile_keys=6144)) > 0
+    assert binar.workspace_bytes(8, 1000, False, params=binar.Params(digit_bits=8, tile_keys=6144)) > 0
+    for kb, k in ((4, 8), (16, 8), (8, 4), (8, 1), (8, 7)):
+        assert binar.workspace_bytes(kb, 1000, True, params=binar.Params(digit_bits=k, tile_keys=6144)) == 0
 
 
 def test_workspace_bytes(lib):
@@ -83,7 +88,7 @@ def test_workspace_bytes(lib):
     assert binar.workspace_bytes(16, 1000, True) > binar.workspace_bytes(4, 1000, True)
     p = binar.default_params(4, True)
     assert p.digit_bits == 8 and p.tile_keys in (2048, 4096, 8192) and p.finish_max > 0
-    assert binar.default_params(8, True).tile_keys in (2048, 4096)
+    assert binar.default_params(8, True).tile_keys in (2048, 4096, 6144)
 
 
 def test_key_kind_params(lib):

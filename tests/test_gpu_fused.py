@@ -48,7 +48,7 @@ def sort_and_check(keys, kb, params):
 def test_second_pass_counts_from_pairs(kb):
     from paper_0811_3448_amd import Params
     keys = workloads.u32_uniform(N, 7001) if kb == 4 else workloads.u64_uniform(N, 7002)
-    tile = 8192 if kb == 4 else 4096
+    tile = 8192 if kb == 4 else 6144
     print("fused pass counts kb=%d n=%d" % (kb, N), flush=True)
     st = sort_and_check(keys, kb, Params(digit_bits=8, tile_keys=tile, offsets=1))
     assert st["passes"] >= 2

@@ -95,6 +95,15 @@ def test_u32_many_chunks(offsets):
     compare(workloads.u32_and4(n, 91), params=P(T=2000, offsets=offsets))
 
 
+@pytest.mark.parametrize("offsets", [1, 2])
+@pytest.mark.parametrize("n", [6143, 6145, 3 * 6144 + 1, 100_003])
+def test_u64_6144_tile(n, offsets):
+    """The 6144-key tile of 8-byte keys (768 threads): ragged last tiles,
+    both offset schemes, several global passes."""
+    compare(workloads.u64_uniform(n, 70), params=P(8, 6144, 64, offsets))
+    compare(workloads.u64_nearly_sorted(n, 71, 0.01), params=P(8, 6144, 64, offsets))
+
+
 @pytest.mark.parametrize("dist", ["uniform", "nearly", "zipf", "dup"])
 @pytest.mark.parametrize("T", [0, 200])
 def test_u64(dist, T):
@@ -222,7 +231,7 @@ def mixed_runs(n, seed, kb=4):
 @pytest.mark.parametrize("k,tile,T", [(8, 8192, 5120), (8, 4096, 64), (4, 2048, 300)])
 def test_mixed_runs(kb, k, tile, T):
     if kb == 8 and tile == 8192:
-        tile = 4096         # the 8192-key tile is built for 4-byte keys only
+        tile = 6144         # 8-byte keys: the largest tile is 6144 keys
     compare(mixed_runs(200_003, 40 + kb + k, kb), params=P(k, tile, T, 1))
 
 

@@ -20,7 +20,7 @@ def test_candidates_are_built_and_complete(kb):
     ks = sorted({p.digit_bits for p in c})
     assert ks == [1, 4, 5, 6, 7, 8]
     tiles = {p.tile_keys for p in c}
-    assert tiles == ({2048, 4096, 8192} if kb == 4 else {2048, 4096})
+    assert tiles == {4: {2048, 4096, 8192}, 8: {2048, 4096, 6144}, 16: {2048, 4096}}[kb]
     assert {p.offsets for p in c} == {1, 2}
     assert len({(p.digit_bits, p.tile_keys, p.finish_max, p.offsets) for p in c}) == len(c)
     tmax = resolve_params(kb, True, Params(finish_max=1 << 30)).finish_max
