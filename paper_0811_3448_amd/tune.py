@@ -194,6 +194,23 @@ class DeviceTimer:
         return bool(torch.equal(self.pristine[p], k))
 
 
+TIE = 0.01  # candidates within this fraction of the fastest count as tied
+
+
+def choose(table: list) -> int:
+    """Index of the winning row of a timing table ([k, tile, T, offsets, ms],
+    ms None for a failed candidate): among the rows within TIE of the
+    fastest, the one with the largest LDS-finish threshold T, then the
+    fastest of those.  A larger T that costs nothing measurable on the tuning
+    keys finishes the larger sub-arrays of other distributions (nearly
+    sorted, skewed) on chip instead of sending them through another global
+    pass."""
+    timed = [i for i in range(len(table)) if table[i][4] is not None]
+    fastest = min(table[i][4] for i in timed)
+    tied = [i for i in timed if table[i][4] <= fastest * (1.0 + TIE)]
+    return min(tied, key=lambda i: (-table[i][2], table[i][4], i))
+
+
 def autotune(key_bytes: int, has_payload: bool, n: int, batched: bool = False,
              timer: Callable[[Params], float] | None = None, cands: list | None = None,
              log: Callable[[str], None] | None = None, **timer_kw) -> dict:
@@ -218,7 +235,7 @@ def autotune(key_bytes: int, has_payload: bool, n: int, batched: bool = False,
     timed = [i for i in range(len(table)) if table[i][4] is not None]
     if not timed:
         raise RuntimeError("autotune: every candidate failed its status or output check")
-    best = min(timed, key=lambda i: (table[i][4], i))
+    best = choose(table)
     k, tile, T, off, ms = table[best]
     return {"params": {"digit_bits": k, "tile_keys": tile, "finish_max": T, "offsets": off},
             "ms": ms, "gkeys_s": round(n / (ms * 1e-3) / 1e9, 4) if ms > 0 else None, "n": n,

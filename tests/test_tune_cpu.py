@@ -36,7 +36,9 @@ def test_autotune_picks_fastest_with_stable_ties():
     cost = {id(p): 10.0 + i for i, p in enumerate(cands)}
     target = cands[17]
     cost[id(target)] = 1.5
-    cost[id(cands[30])] = 1.5          # a tie: the earlier candidate wins
+    # a tie with the same finish threshold: the earlier candidate wins
+    twin = next(p for p in cands[18:] if p.finish_max == target.finish_max)
+    cost[id(twin)] = 1.5
     e = tune.autotune(4, True, 1 << 20, timer=lambda p: cost[id(p)], cands=cands)
     assert e["params"] == {"digit_bits": target.digit_bits, "tile_keys": target.tile_keys,
                            "finish_max": target.finish_max, "offsets": target.offsets}
@@ -45,6 +47,24 @@ def test_autotune_picks_fastest_with_stable_ties():
     assert e["workgroup"] == tune.TILE_THREADS[target.tile_keys]
     with pytest.raises(ValueError):
         tune.autotune(4, True, 1, timer=lambda p: 1.0)
+
+
+def test_ties_within_a_percent_prefer_the_larger_finish_threshold():
+    # [k, tile, T, offsets, ms]
+    t = [[8, 4096, 3072, 1, 1.000], [8, 4096, 5120, 1, 1.009], [8, 4096, 8192, 1, 1.02],
+         [8, 2048, 5120, 1, 1.005], [8, 4096, 8192, 2, None]]
+    assert tune.choose(t) == 3          # tied: T = 5120 beats 3072; of the two 5120 rows the faster
+    t[3][4] = 1.2
+    assert tune.choose(t) == 1
+    t[1][4] = 1.011                     # past 1%: the fastest stands
+    assert tune.choose(t) == 0
+    cands = tune.candidates(8, True)
+    big = max(p.finish_max for p in cands)
+    fast = next(p for p in cands if p.finish_max < big)
+    slow = next(p for p in cands if p.finish_max == big)
+    cost = {id(p): 10.0 for p in cands}
+    cost[id(fast)], cost[id(slow)] = 2.0, 2.015
+    assert tune.autotune(8, True, 1 << 20, timer=lambda p: cost[id(p)], cands=cands)["params"]["finish_max"] == big
 
 
 def test_cache_roundtrip_and_lookup(tmp_path):
