@@ -33,6 +33,12 @@ sorting permutation (int32 holding uint32 indices into the request).
   views of that batch's output tensors (keys, permutation); its budget is
   released and its Future set.
 * Cancelling a Future before its batch starts frees its budget.
+* Streams: a lane's resident buffers are made and filled on the lane's own
+  stream, and a batch's outputs are allocated there.  A Future is set only
+  once its batch has finished on the device, so its tensors can be read on
+  any stream; a caller that reads them asynchronously on another stream and
+  then drops them calls ``record_stream`` for that stream first (torch's
+  caching allocator hands freed memory back to the lane's stream at once).
 
 One scheduler thread does admission, packing, launches and completion; the
 device work lives in a backend object (``DeviceBackend``), so the policy can
@@ -386,13 +392,18 @@ class _Lane:
         from .binar import Plan
         self.kb, self.kind, self.cap, self.max_segments = kb, kind, cap, max_segments
         self.stream = torch.cuda.Stream(device=device)
-        if kb == 16:
-            self.keys = torch.empty((cap, 16), dtype=torch.uint8, device=device)
-        else:
-            self.keys = torch.empty(cap, dtype=torch.int32 if kb == 4 else torch.int64, device=device)
-        self.pay = torch.empty(cap, dtype=torch.int32, device=device)
-        self.iota = torch.arange(cap, dtype=torch.int32, device=device)
-        self.off_dev = torch.zeros(max_segments + 1, dtype=torch.int32, device=device)
+        # allocated and filled on the lane's own stream, which every batch
+        # runs on: the stream of the thread that makes the lane is not
+        # ordered with it (filled there, the first batch could copy the
+        # permutation's start from memory arange had not written yet)
+        with torch.cuda.stream(self.stream):
+            if kb == 16:
+                self.keys = torch.empty((cap, 16), dtype=torch.uint8, device=device)
+            else:
+                self.keys = torch.empty(cap, dtype=torch.int32 if kb == 4 else torch.int64, device=device)
+            self.pay = torch.empty(cap, dtype=torch.int32, device=device)
+            self.iota = torch.arange(cap, dtype=torch.int32, device=device)
+            self.off_dev = torch.zeros(max_segments + 1, dtype=torch.int32, device=device)
         self.off_host = torch.zeros(max_segments + 1, dtype=torch.int32, pin_memory=True)
         self.status = torch.zeros(2, dtype=torch.int32, pin_memory=True)
         self.plan = Plan(kb, cap, max_segments, True, params)

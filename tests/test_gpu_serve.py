@@ -76,6 +76,24 @@ def test_alone_equals_in_mix():
     check_against_alone(host, dev, res)
 
 
+def test_first_batch_while_the_default_stream_is_busy():
+    """A lane is made, and its first batch runs, while the default stream
+    (which the thread that makes the lane would use) still has queued work:
+    the lane fills its resident buffers on its own stream, so the answer is
+    right.  (Filled on the default stream, the permutation buffer could be
+    read by the batch before it was written.)"""
+    import torch
+    from paper_0811_3448_amd.serve import Server
+    a = workloads.u32_uniform(200_000, 4321)
+    t = torch.from_numpy(a.view(np.int32)).pin_memory()
+    with Server(budget_bytes=4 << 30, streams=1, max_batch_keys=1 << 21) as srv:
+        torch.cuda._sleep(50_000_000)   # a bounded spin queued on the default stream
+        r = srv.submit(t).result(timeout=120)
+    order = np.argsort(a, kind="stable")
+    assert np.array_equal(r.perm.cpu().numpy(), order.astype(np.int32))
+    assert np.array_equal(r.keys.cpu().numpy().view(np.uint32), a[order])
+
+
 def kb_of(a):
     return 4 if a.dtype == np.uint32 else (8 if a.dtype == np.uint64 else 16)
 
