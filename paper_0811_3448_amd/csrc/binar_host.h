@@ -41,20 +41,21 @@ inline size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
 constexpr int HIST_BT = 1024;
 
 // LDS-finish classes per key width: (threads per block, keys per thread);
-// capacities 1024, 3072, 5120, 8192 keys (8-byte keys: 1024, 2304, 5120,
+// capacities 1024, 2048, 5120, 8192 keys (8-byte keys: 1024, 2304, 5120,
 // 8192; 16-byte keys: 1024, 2048, 3072, 5120).  The finish is bound by LDS
 // work: 256-thread blocks let several independent blocks share a CU, so one
 // block's loads and stores overlap another's LDS passes.  Where even a
 // 256-thread block is alone on its CU (the largest class of 8- and 16-byte
 // keys), 512 threads keep more waves.  The second class of 8-byte keys
 // holds 2304 (40 KiB of LDS: four blocks a CU), which takes the 2048-key
-// sub-arrays that two 8-bit passes leave of 2^27 uniform keys.
+// sub-arrays that two 8-bit passes leave of 2^27 uniform keys; that of
+// 4-byte keys holds 2048 (28 KiB: five blocks a CU).
 template <int KB>
 struct FinShape;
 template <>
 struct FinShape<4> {
     static constexpr int bt[NCLASS] = {256, 256, 256, 256};
-    static constexpr int items[NCLASS] = {4, 12, 20, 32};
+    static constexpr int items[NCLASS] = {4, 8, 20, 32};
 };
 template <>
 struct FinShape<8> {

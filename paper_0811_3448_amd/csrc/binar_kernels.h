@@ -1990,13 +1990,15 @@ __device__ bool fix_runs(FinishLds<KB, BT, ITEMS, PAY> &S, int pe, uint32_t len,
 }
 
 // Waves per SIMD that the register budget must allow for a finish class:
-// as many blocks as fit a CU by LDS (160 KiB), at most 4 waves (a higher
-// floor makes the keys-only classes spill).
+// as many blocks as fit a CU by LDS (160 KiB), capped below.
 template <int KB, int BT, int ITEMS, bool PAY>
 struct FinOcc {
     static constexpr int blocks = (160 * 1024) / (int)sizeof(FinishLds<KB, BT, ITEMS, PAY>);
     static constexpr int lds_waves = (blocks * (BT / WAVE) + 3) / 4;
-    static constexpr int waves = lds_waves < 4 ? lds_waves : 4;
+    // at most 4 (5 for a class of 8 keys a thread with a payload, whose
+    // LDS fits five blocks): a higher floor makes the keys-only classes spill
+    static constexpr int cap = (ITEMS <= 8 && PAY) ? 5 : 4;
+    static constexpr int waves = lds_waves < cap ? lds_waves : cap;
 };
 
 template <int KB, int BT, int ITEMS, bool PAY>

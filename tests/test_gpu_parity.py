@@ -155,10 +155,10 @@ def test_segmented_small(T):
 @pytest.mark.parametrize("kb", [4, 8, 16])
 def test_finish_class_boundaries(kb):
     """Segments exactly at and just past every LDS-finish class capacity
-    (1024, 3072, 5120, 8192 keys; 8-byte keys 1024, 2304, 5120, 8192;
+    (4-byte keys 1024, 2048, 5120, 8192; 8-byte keys 1024, 2304, 5120, 8192;
     16-byte keys 1024, 2048, 3072, 5120), at unaligned offsets, each
     finished by its class or split by a pass."""
-    caps = {4: [1024, 3072, 5120, 8192], 8: [1024, 2304, 5120, 8192], 16: [1024, 2048, 3072, 5120]}[kb]
+    caps = {4: [1024, 2048, 5120, 8192], 8: [1024, 2304, 5120, 8192], 16: [1024, 2048, 3072, 5120]}[kb]
     lens = []
     for c in caps:
         lens += [c - 1, c, c + 1]
