@@ -194,7 +194,7 @@ class DeviceTimer:
         return bool(torch.equal(self.pristine[p], k))
 
 
-TIE = 0.01  # candidates within this fraction of the fastest count as tied
+TIE = 0.02  # candidates within this fraction of the fastest count as tied
 
 
 def choose(table: list) -> int:
@@ -204,7 +204,8 @@ def choose(table: list) -> int:
     fastest of those.  A larger T that costs nothing measurable on the tuning
     keys finishes the larger sub-arrays of other distributions (nearly
     sorted, skewed) on chip instead of sending them through another global
-    pass."""
+    pass.  TIE is about the spread of the median of three timings between
+    thresholds that do the same work on uniform keys."""
     timed = [i for i in range(len(table)) if table[i][4] is not None]
     fastest = min(table[i][4] for i in timed)
     tied = [i for i in timed if table[i][4] <= fastest * (1.0 + TIE)]

@@ -49,14 +49,15 @@ def test_autotune_picks_fastest_with_stable_ties():
         tune.autotune(4, True, 1, timer=lambda p: 1.0)
 
 
-def test_ties_within_a_percent_prefer_the_larger_finish_threshold():
+def test_ties_within_the_band_prefer_the_larger_finish_threshold():
     # [k, tile, T, offsets, ms]
-    t = [[8, 4096, 3072, 1, 1.000], [8, 4096, 5120, 1, 1.009], [8, 4096, 8192, 1, 1.02],
+    t = [[8, 4096, 3072, 1, 1.000], [8, 4096, 5120, 1, 1.018], [8, 4096, 8192, 1, 1.03],
          [8, 2048, 5120, 1, 1.005], [8, 4096, 8192, 2, None]]
+    assert tune.TIE == 0.02
     assert tune.choose(t) == 3          # tied: T = 5120 beats 3072; of the two 5120 rows the faster
     t[3][4] = 1.2
     assert tune.choose(t) == 1
-    t[1][4] = 1.011                     # past 1%: the fastest stands
+    t[1][4] = 1.021                     # past the band: the fastest stands
     assert tune.choose(t) == 0
     cands = tune.candidates(8, True)
     big = max(p.finish_max for p in cands)
