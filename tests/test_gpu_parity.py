@@ -152,6 +152,25 @@ def test_segmented_small(T):
     assert np.array_equal(gp, rp)
 
 
+@pytest.mark.parametrize("offsets", [1, 2])
+def test_segmented_u64_6144_tile(offsets):
+    """Segments of 8-byte keys through the 6144-key tile: lognormal sizes up
+    to several tiles, an empty and a one-key segment, chunk prefixes or
+    look-back across a segment's tiles, several global passes (T = 64)."""
+    _, off = workloads.batched_u32(200, seed=73, median=3000, sigma=1.0, max_len=40_000)
+    n = int(off[-1])
+    keys = workloads.u64_uniform(n, 74)
+    off = off.copy()
+    off[10] = off[9]            # empty segment
+    off[20] = off[19] + 1       # one-key segment
+    off = np.maximum.accumulate(off)
+    print("segmented u64 tile 6144 n=%d offsets=%d" % (n, offsets), flush=True)
+    gk, gp = gpu_sort_segmented(keys, off, iota(n), params=P(8, 6144, 64, offsets))
+    rk, rp = oracle.sort_segmented(keys, off, iota(n))
+    assert np.array_equal(gk, rk)
+    assert np.array_equal(gp, rp)
+
+
 @pytest.mark.parametrize("kb", [4, 8, 16])
 def test_finish_class_boundaries(kb):
     """Segments exactly at and just past every LDS-finish class capacity
